@@ -1,0 +1,26 @@
+"""CPU oracle for ML(n)BiCGStab (test infrastructure only).
+
+A plain, slow, fp64 / complex128 implementation of what the GPU library
+computes, written from the paper (Yeung, "An introduction to ML(n)BiCGStab",
+arXiv 1106.3678).  Only the tests, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it; the GPU library never
+does, and the two share no code.
+
+Modules:
+  index      -- the index functions g_n, r_n (Section 2, Table 2.1)
+  mlbicgstabt-- ML(n)BiCGStabt, Algorithm 7.1 (preconditioned form of
+                Algorithm 4.1) in its i/j loop form; M = I unless given
+  mlbicg     -- ML(n)BiCG, Algorithm 3.1 (only used to pin the oracle)
+  iterative_refinement -- fp64 refinement around a lower-precision inner solve
+                (an addition of this library, not in the paper)
+
+Parity status: every function is pinned by a CPU test (Table 2.1, n=1 equals
+BiCGStab, finite termination against LU, FOM/GMRES relations, Algorithm 3.1
+and eq. (4.1), Table 4.3 operation counts) except the paper's sample execution
+(Section 7), which prints no outputs: parity unpinned.
+"""
+from .index import g_n, r_n
+from .mlbicgstabt import OpCounter, Result, mlbicgstabt, true_error
+from .mlbicg import mlbicg
+
+__all__ = ["g_n", "r_n", "OpCounter", "Result", "mlbicgstabt", "true_error", "mlbicg"]

@@ -1,0 +1,353 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix (no GPU)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import workloads
+from oracle import OpCounter, g_n, mlbicg, mlbicgstabt, r_n, true_error
+from tests import textbook
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- small systems
+
+
+def dd_dense(N, seed, complex_=False, dominance=2.0):
+    """Tiny dense, diagonally dominant, nonsymmetric matrix."""
+    g = np.random.default_rng(seed)
+    A = g.standard_normal((N, N))
+    if complex_:
+        A = A + 1j * g.standard_normal((N, N))
+    A = A / np.sqrt(N)
+    A = A + dominance * np.eye(N)
+    return A
+
+
+def vec(N, seed, complex_=False):
+    g = np.random.default_rng(seed)
+    v = g.standard_normal(N)
+    if complex_:
+        v = v + 1j * g.standard_normal(N)
+    return v
+
+
+def block(N, n, seed, complex_=False):
+    g = np.random.default_rng(seed)
+    Q = g.standard_normal((N, n))
+    if complex_:
+        Q = Q + 1j * g.standard_normal((N, n))
+    return np.asfortranarray(Q)
+
+
+# --------------------------------------------------------------------------- Section 2
+
+
+def test_index_table_2_1():
+    """Table 2.1 (n = 3, k = 0..12), read from the golden fixture."""
+    lines = [l.split() for l in open(os.path.join(GOLDEN, "table_2_1.txt")) if l.strip() and l[0] != "#"]
+    n = int(lines[0][1])
+    rows = [tuple(map(int, l)) for l in lines[1:]]
+    assert len(rows) == 13
+    for k, g, r in rows:
+        assert g_n(n, k) == g and r_n(n, k) == r, (k, g, r)
+
+
+@pytest.mark.parametrize("n", list(range(1, 17)))
+def test_index_split_identity(n):
+    """k = j n + i with 1 <= i <= n gives g_n(k) = j, r_n(k) = i (eq. (2.1)), also for k <= 0."""
+    for j in range(-6, 7):
+        for i in range(1, n + 1):
+            k = j * n + i
+            assert g_n(n, k) == j and r_n(n, k) == i
+    for k in range(-50, 51):
+        assert 1 <= r_n(n, k) <= n
+
+
+# --------------------------------------------------------------------------- n = 1 is BiCGStab
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_n1_is_bicgstab(complex_):
+    """Section 4.3: Algorithm 4.1 with n = 1 is BiCGStab (iterate by iterate)."""
+    if complex_:
+        A = workloads.helmholtz_3d(6, pe=2.0, k=3.0, gen=workloads.rng(99, 0))
+    else:
+        A = workloads.convdiff_2d(10, pe=3.0)
+    N = A.shape[0]
+    b = vec(N, 1, complex_)
+    q = vec(N, 2, complex_)
+    res = mlbicgstabt(A, b, q[:, None], tol=1e-10, maxit=500, record_x=10 ** 6)
+    xs, it, flag = textbook.bicgstab(A, b, q, tol=1e-10, maxit=500)
+    assert res.flag == 0 and flag == 0
+    assert res.iter == it
+    for k in range(min(30, it)):
+        rel = np.linalg.norm(res.x_history[k] - xs[k]) / np.linalg.norm(xs[k])
+        assert rel < 1e-10, (k, rel)
+
+
+# --------------------------------------------------------------------------- finite termination
+
+
+@pytest.mark.parametrize("N", [4, 7, 12])
+@pytest.mark.parametrize("extra", [0, 3])
+@pytest.mark.parametrize("complex_", [False, True])
+def test_finite_termination(N, extra, complex_):
+    """With n >= N the residual is orthogonal to q_1..q_k after k steps, so r_N = 0."""
+    A = dd_dense(N, 10 + N, complex_)
+    b = vec(N, 20 + N, complex_)
+    Q = block(N, N + extra, 30 + N, complex_)
+    res = mlbicgstabt(A, b, Q, tol=1e-10, maxit=10 * N)
+    assert res.flag == 0
+    assert res.iter == N
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(res.x - xs) / np.linalg.norm(xs) < 1e-10
+
+
+# --------------------------------------------------------------------------- Algorithm 3.1 and its relations
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_mlbicg_fom_relation(complex_):
+    """Section 3: with n >= N and q_k = hat r_{k-1}, Algorithm 3.1 is FOM."""
+    N = 8
+    A = dd_dense(N, 3, complex_)
+    b = vec(N, 4, complex_)
+    xs, _ = mlbicg(A, b, block(N, N + 1, 5, complex_), steps=N - 1, q_update=lambda k, r: r.copy())
+    for k in range(1, N):
+        ref = textbook.fom_iterate(A, b, k)
+        assert np.linalg.norm(xs[k] - ref) / np.linalg.norm(ref) < 1e-9, k
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_mlbicg_gmres_relation(complex_):
+    """Section 3: with n >= N and q_k = A hat r_{k-1}, Algorithm 3.1 is GMRES."""
+    N = 8
+    A = dd_dense(N, 6, complex_)
+    b = vec(N, 7, complex_)
+    xs, _ = mlbicg(A, b, block(N, N + 1, 8, complex_), steps=N - 1, q_update=lambda k, r: A @ r)
+    for k in range(1, N):
+        ref = textbook.gmres_iterate(A, b, k)
+        assert np.linalg.norm(xs[k] - ref) / np.linalg.norm(ref) < 1e-9, k
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_mlbicg_n1_is_bicg(complex_):
+    """Section 3: with n = 1, Algorithm 3.1 is BiCG."""
+    N = 10
+    A = dd_dense(N, 9, complex_, dominance=3.0)
+    b = vec(N, 10, complex_)
+    q = vec(N, 11, complex_)
+    xs, _ = mlbicg(A, b, q[:, None], steps=6)
+    ref = textbook.bicg(A, b, q, steps=6)
+    for k in range(1, 7):
+        assert np.linalg.norm(xs[k] - ref[k]) / np.linalg.norm(ref[k]) < 1e-9, k
+
+
+@pytest.mark.parametrize("mode", ["fom", "gmres"])
+@pytest.mark.parametrize("complex_", [False, True])
+def test_oracle_fom_gmres(mode, complex_):
+    """ML(n)BiCGStabt with n > N and adaptive shadows reproduces FOM / GMRES in cycle 0."""
+    N = 7
+    A = dd_dense(N, 12, complex_)
+    b = vec(N, 13, complex_)
+    upd = (lambda k, r: r.copy()) if mode == "fom" else (lambda k, r: A @ r)
+    res = mlbicgstabt(A, b, block(N, N + 2, 14, complex_), tol=1e-13, maxit=100, record_x=N, q_update=upd)
+    ref_fn = textbook.fom_iterate if mode == "fom" else textbook.gmres_iterate
+    for k in range(1, N):
+        ref = ref_fn(A, b, k)
+        assert np.linalg.norm(res.x_history[k - 1] - ref) / np.linalg.norm(ref) < 1e-9, k
+
+
+def _omega_poly(A, omegas, j, v):
+    """Omega_j(A) v with Omega_0 = 1, Omega_m(lambda) = (1 - omega_m lambda) Omega_{m-1}(lambda)."""
+    for m in range(j):
+        v = v - omegas[m] * (A @ v)
+    return v
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("complex_", [False, True])
+def test_residual_definition_eq_4_1(n, complex_):
+    """r_k = Omega_{g_n(k+1)}(A) hat r_k (eq. (4.1)), hat r_k from Algorithm 3.1 on the same Q.
+
+    For k <= n-1 (cycle 0) this says ML(n)BiCGStabt reproduces Algorithm 3.1.
+    """
+    N = 24
+    A = dd_dense(N, 40 + n, complex_, dominance=2.5)
+    b = vec(N, 41, complex_)
+    Q = block(N, n, 42, complex_)
+    K = 3 * n
+    res = mlbicgstabt(A, b, Q, tol=1e-30, maxit=K, record_x=K)
+    assert len(res.x_history) == K
+    _, rhat = mlbicg(A, b, Q, steps=K)
+    for k in range(1, K + 1):
+        rk = b - A @ res.x_history[k - 1]
+        ref = _omega_poly(A, res.omegas, g_n(n, k + 1), rhat[k])
+        tol = 1e-8 * np.linalg.norm(ref) + 1e-13 * np.linalg.norm(b)
+        assert np.linalg.norm(rk - ref) < tol, (k, n)
+
+
+# --------------------------------------------------------------------------- Table 4.3
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8])
+def test_table_4_3_operation_counts(n):
+    """Per steady cycle (j >= 1): matvec n+1, precond n+1, dot n^2+n+2, saxpy 1.5n^2+2.5n+2, scale n.
+
+    Divided by n these are Table 4.3's per-iteration averages.
+    """
+    A = workloads.convdiff_2d(12, pe=2.0)
+    N = A.shape[0]
+    cnt = OpCounter()
+    res = mlbicgstabt(A, vec(N, 1), block(N, n, 2), tol=1e-300, maxit=4 * n + 1, counter=cnt)
+    assert res.flag == 1
+    marks = dict((lab[1], c) for lab, c in cnt.marks)
+    d = {key: marks[2][key] - marks[1][key] for key in OpCounter.KEYS}
+    assert d["matvec"] == n + 1
+    assert d["precond"] == n + 1
+    assert d["dot"] == n * n + n + 2
+    assert 2 * d["saxpy"] == 3 * n * n + 5 * n + 4
+    assert d["scale"] == n
+    assert d["norm"] == n + 1
+
+
+# --------------------------------------------------------------------------- biorthogonality
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_biorthogonality(n):
+    """After step i, q_s^H w = 0 for s < i; after a beta~ recurrence, q_s^H z_w = 0 for s >= i."""
+    A = workloads.convdiff_2d(10, pe=2.0)
+    N = A.shape[0]
+    Q = block(N, n, 3)
+    worst = []
+
+    def obs(event, **st):
+        Qm = st["Q"]
+        if event == "w":
+            i = st["col"]
+            w = st["W"][:, i]
+            for s in range(i):
+                worst.append(abs(np.vdot(Qm[:, s], w)) / (np.linalg.norm(Qm[:, s]) * np.linalg.norm(w)))
+        else:
+            i = st["col"]
+            zw = st["zw"]
+            for s in range(i, n):
+                worst.append(abs(np.vdot(Qm[:, s], zw)) / (np.linalg.norm(Qm[:, s]) * np.linalg.norm(zw)))
+
+    mlbicgstabt(A, vec(N, 4), Q, tol=1e-300, maxit=3 * n, observer=obs)
+    assert worst and max(worst) < 1e-10
+
+
+# --------------------------------------------------------------------------- flags and edge cases
+
+
+def test_flag_breakdown_c_zero():
+    A = np.eye(3)
+    b = np.array([1.0, 0.0, 0.0])
+    Q = np.array([[0.0], [1.0], [0.0]])
+    res = mlbicgstabt(A, b, Q, tol=1e-10, maxit=10)
+    assert res.flag == -1 and res.iter == 0
+
+
+def test_flag_breakdown_omega_zero():
+    A = np.array([[0.0, 1.0], [-1.0, 0.0]])
+    b = np.array([1.0, 0.0])
+    Q = np.array([[1.0], [1.0]])
+    res = mlbicgstabt(A, b, Q, tol=1e-10, maxit=10)
+    assert res.flag == -1 and res.iter == 0
+
+
+def test_flag_maxit():
+    A = workloads.convdiff_2d(8, pe=1.0)
+    N = A.shape[0]
+    res = mlbicgstabt(A, vec(N, 1), block(N, 3, 2), tol=1e-10, maxit=1)
+    assert res.flag == 1 and res.iter == 1
+
+
+def test_zero_rhs_and_exact_guess():
+    A = workloads.convdiff_2d(8, pe=1.0)
+    N = A.shape[0]
+    res = mlbicgstabt(A, np.zeros(N), block(N, 3, 2), tol=1e-10, maxit=10)
+    assert res.flag == 0 and res.iter == 0 and not res.x.any()
+    xs = vec(N, 3)
+    b = A @ xs
+    res = mlbicgstabt(A, b, block(N, 3, 2), x0=xs, tol=1e-10, maxit=10)
+    assert res.flag == 0 and res.iter == 0
+
+
+def test_half_step_exit():
+    """A solve that meets the tolerance on the half step of a cycle end stops there (k = jn + n)."""
+    N = 5
+    A = dd_dense(N, 77)
+    b = vec(N, 78)
+    res = mlbicgstabt(A, b, block(N, N, 79), tol=1e-10, maxit=50)
+    assert res.flag == 0 and res.iter == N
+    assert res.iter % N == 0
+
+
+# --------------------------------------------------------------------------- stability and final solution
+
+
+@pytest.mark.parametrize("n", [1, 4, 8])
+def test_config1_solution_vs_lu(n):
+    """Workload 1 (2D convection-diffusion, N = 1024): oracle solution vs a sparse LU solve."""
+    p = workloads.config1(n=n)
+    res = mlbicgstabt(p.A, p.b, p.Q, tol=p.tol, maxit=p.maxit)
+    assert res.flag == 0
+    xs = spla.splu(p.A.tocsc()).solve(p.b)
+    assert np.linalg.norm(res.x - xs) / np.linalg.norm(xs) < 1e-7
+    # Section 5.1: the third algorithm's recursive residual tracks the true one.
+    assert true_error(p.A, res.x, p.b) < 2 * p.tol
+
+
+def test_small_3d_solution_vs_lu():
+    p = workloads.config2(n=4, m=16)
+    res = mlbicgstabt(p.A, p.b, p.Q, tol=p.tol, maxit=p.maxit)
+    assert res.flag == 0
+    xs = spla.splu(p.A.tocsc()).solve(p.b)
+    assert np.linalg.norm(res.x - xs) / np.linalg.norm(xs) < 1e-7
+    assert true_error(p.A, res.x, p.b) < 2 * p.tol
+
+
+def test_bsr3_small_vs_lu():
+    p = workloads.config3(n=4, grid=(8, 10, 6))
+    res = mlbicgstabt(p.A, p.b, p.Q, tol=p.tol, maxit=p.maxit)
+    assert res.flag == 0
+    xs = spla.splu(p.A.tocsc()).solve(p.b)
+    assert np.linalg.norm(res.x - xs) / np.linalg.norm(xs) < 1e-6
+    assert true_error(p.A, res.x, p.b) < 2 * p.tol
+
+
+def test_complex_small_vs_lu():
+    p = workloads.config5(n=8, m=10)
+    res = mlbicgstabt(p.A, p.b, p.Q, tol=p.tol, maxit=p.maxit)
+    assert res.flag == 0
+    xs = spla.splu(p.A.tocsc()).solve(p.b)
+    assert np.linalg.norm(res.x - xs) / np.linalg.norm(xs) < 1e-7
+    assert true_error(p.A, res.x, p.b) < 2 * p.tol
+
+
+def test_sample_execution_section_7():
+    """The paper's sample call (Section 7): N = 100 random A and M, n = 10, kappa = 0.7.
+
+    The paper prints no outputs for it, so this only checks that the call runs and
+    that a converged run really solves the system: parity unpinned.
+    """
+    g = np.random.default_rng(1106)
+    N = 100
+    A = g.standard_normal((N, N))
+    M = g.standard_normal((N, N))
+    b = g.standard_normal(N)
+    n = 10
+    Q = np.sign(g.standard_normal((N, n)))
+    Q[:, 0] = b
+    pre = (lambda v: np.linalg.solve(M, v), lambda v: np.linalg.solve(M.conj().T, v))
+    res = mlbicgstabt(A, b, Q, tol=1e-7, maxit=3 * N, kappa=0.7, precond=pre)
+    assert res.flag in (0, 1, -1)
+    if res.flag == 0:
+        assert true_error(A, res.x, b) < 1e-5
