@@ -1,0 +1,161 @@
+/*
+ * mlbicgstab.h -- C ABI of the MI355X (gfx950) ML(n)BiCGStab library.
+ *
+ * The library solves sparse A x = b with ML(n)BiCGStabt, the A^H-using
+ * ML(n)BiCGStab algorithm of M.-C. Yeung, "An introduction to ML(n)BiCGStab"
+ * (arXiv 1106.3678): Algorithm 4.1 (Section 4.3), in the i/j loop form of
+ * Algorithm 7.1 (Section 7) with M = I.  Every iteration runs in hand-written
+ * HIP kernels on one GPU; scalars and convergence control stay on the device.
+ *
+ * Conventions shared by every entry point
+ *  - Array pointers named "device" point to GPU memory of the current HIP
+ *    device; the caller owns them.  A's arrays are borrowed from create()
+ *    until destroy(); b, x and Q are borrowed for the duration of one solve().
+ *  - Work is ordered on the HIP stream passed to create() (NULL = the legacy
+ *    default stream).  solve() returns after the result is complete (it
+ *    synchronises that stream once at the end).
+ *  - Complex values are two consecutive doubles (re, im), i.e. C99
+ *    `double _Complex` / numpy complex128 layout.  u^H v conjugates u.
+ *  - Return codes: >= -1 is the paper's flag (0 converged, 1 maxit reached,
+ *    -1 breakdown); <= -2 is an API error (MLB_E*), with a message available
+ *    from mlbicgstab_last_error() on the calling thread.  No C++ exception
+ *    crosses this boundary.  On an API error nothing was written to x.
+ */
+#ifndef MLBICGSTAB_H
+#define MLBICGSTAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mlb_solver* mlb_handle;
+
+/* Return codes.  0 / 1 / -1 are the flag of Algorithm 7.1's realisation. */
+enum {
+  MLB_CONVERGED = 0,      /* recursive ||r|| / ||b|| < tol                    */
+  MLB_MAXIT = 1,          /* maxit iterations done without convergence         */
+  MLB_BREAKDOWN = -1,     /* c_k == 0, ||A u||^2 == 0 or omega == 0 (or non-finite) */
+  MLB_EINVAL = -2,        /* bad argument (null pointer, size, enum value)     */
+  MLB_ENOMEM = -3,        /* device or pinned host allocation failed           */
+  MLB_EHIP = -4,          /* a HIP runtime call failed                         */
+  MLB_EUNSUPPORTED = -5   /* valid but not supported (e.g. n > MLB_MAX_N)      */
+};
+
+enum { MLB_R64 = 0, MLB_C128 = 1 };          /* value type of A, b, x, Q        */
+enum { MLB_CSR = 0, MLB_BSR3 = 1 };          /* storage of A                     */
+enum { MLB_PREC_FP64 = 0, MLB_PREC_FP32_IR = 1 };
+
+#define MLB_MAX_N 32                          /* largest number of shadow vectors */
+
+/*
+ * A sparse square matrix on the device.
+ *  CSR  : row_ptr[nrows+1], col_idx[nnz], values[nnz]; column indices of a
+ *         row need not be sorted; duplicates are summed.
+ *  BSR3 : 3x3 blocks.  nrows = 3 * (block rows); nnz = number of stored
+ *         blocks; row_ptr[nrows/3+1] and col_idx[nnz] index blocks; values
+ *         holds nnz blocks of 9 entries each, row-major inside a block.
+ * Indices are 0-based int32; row_ptr[0] must be 0 and row_ptr[last] = nnz.
+ */
+typedef struct {
+  int32_t format;           /* MLB_CSR or MLB_BSR3                             */
+  int32_t dtype;            /* MLB_R64 or MLB_C128                             */
+  int64_t nrows;            /* N, scalar rows (= columns)                       */
+  int64_t nnz;              /* stored entries (CSR) or stored blocks (BSR3)    */
+  const int32_t* row_ptr;   /* device                                          */
+  const int32_t* col_idx;   /* device                                          */
+  const void* values;       /* device                                          */
+} mlb_matrix;
+
+/*
+ * Solver options.  n, tol, maxit and kappa are the paper's arguments
+ * (Section 7): n = number of shadow vectors (columns of Q), 1 <= n <= 32;
+ * tol > 0 for the recursive residual test; maxit >= 1; kappa >= 0 selects
+ * the omega guard of eq. (5.1) (0 = plain minimisation).
+ *
+ * precision = MLB_PREC_FP32_IR runs the Krylov iteration in fp32 (fp32
+ * vectors, fp32 SpMV / dot accumulation, fp64 coefficient recurrences) inside
+ * an fp64 iterative-refinement loop (r = b - A x, x += d in fp64) that stops
+ * on the TRUE residual ||b - A x|| / ||b|| < tol.  This mode is an addition of
+ * this library; the paper does not discuss precision.  inner_tol (default
+ * 1e-5 when <= 0) is the relative tolerance of each inner solve and
+ * max_outer (default 30 when <= 0) bounds the refinement steps; if a
+ * refinement step gains less than 10x, or an inner solve breaks down, the
+ * remaining work is done by the fp64 iteration.
+ *
+ * record_iterates = K > 0 stores x_1 .. x_K (K <= maxit) in the device array
+ * iterates (N x K, column-major, ld = N, same dtype as x) during an fp64 solve.
+ */
+typedef struct {
+  int32_t n;
+  double tol;
+  int64_t maxit;
+  double kappa;
+  int32_t precision;
+  double inner_tol;
+  int32_t max_outer;
+  int32_t record_iterates;
+  void* iterates;           /* device, N x record_iterates, or NULL            */
+} mlb_options;
+
+typedef struct {
+  int32_t flag;             /* same as the return code when >= -1              */
+  int64_t iter;             /* k at exit (fp64), or total inner iterations (IR) */
+  int32_t outer_iters;      /* refinement steps (IR), 0 for fp64               */
+  int64_t fp64_iters;       /* iterations run by the fp64 iteration             */
+  double err_recursive;     /* recursive ||r_k|| / ||b|| at exit (fp64 iteration) */
+  double err_true;          /* ||b - A x|| / ||b|| recomputed in fp64 at exit   */
+  double setup_ms;          /* residual, F = A^H Q, first w (stream time)       */
+  double solve_ms;          /* whole solve() call, stream time                  */
+} mlb_result;
+
+/*
+ * Create a solver for A with the given options.  Builds the conjugate
+ * transpose A^H (Algorithm 4.1, step 2 needs A^H q_s) as an explicit device
+ * copy, allocates the Krylov workspace ((4n+4) N values plus O(n^2)
+ * scalars, Table 4.3) and, for MLB_PREC_FP32_IR, fp32 copies of A and A^H.
+ * hip_stream: a hipStream_t (NULL = default stream).  On success *out holds
+ * the handle; on error *out is NULL.
+ */
+int mlbicgstab_create(const mlb_matrix* A, const mlb_options* opt, void* hip_stream, mlb_handle* out);
+
+/* Bytes of device memory create() would allocate for A and opt. */
+int mlbicgstab_workspace_size(const mlb_matrix* A, const mlb_options* opt, size_t* bytes);
+
+/*
+ * Solve A x = b.  b: device, N values.  x: device, N values; in = x_0,
+ * out = the solution (the half-step x when the solve stops on the half step
+ * that ends a cycle, as in Algorithm 7.1's realisation).  Q: device,
+ * N x n shadow block [q_1 .. q_n], column-major with leading dimension
+ * ldq >= N.  res may be NULL.  Returns the flag (0, 1, -1) or an API error.
+ */
+int mlbicgstab_solve(mlb_handle h, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res);
+
+/* Free everything create() allocated.  NULL is accepted. */
+int mlbicgstab_destroy(mlb_handle h);
+
+/* Message for the last API error on this thread ("" if none). */
+const char* mlbicgstab_last_error(void);
+
+/*
+ * Kernel timing for roofline figures: launches the solver's SpMV kernel
+ * (w = A g with its fused combination and shadow dot products, as one inner
+ * step of the fp64 iteration launches it) `reps` times on the solver's stream
+ * over the workspace left by the last solve, bracketed by HIP events, and
+ * stores the mean duration in *ms_per_launch.  Requires a prior solve().
+ * The workspace contents are scrambled afterwards.
+ */
+int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* ms_per_launch);
+
+enum {
+  MLB_KERNEL_SPMV_STEP = 0,   /* SpMV + combination + multi-dot of an inner step */
+  MLB_KERNEL_ALPHA_STEP = 1,  /* x, r update + norm + multi-dot                   */
+  MLB_KERNEL_COMBINE = 2      /* beta~ combination + F multi-dot                  */
+};
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLBICGSTAB_H */

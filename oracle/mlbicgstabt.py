@@ -38,6 +38,7 @@ Table 4.3 operation counts per steady cycle.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -83,12 +84,22 @@ def true_error(A, x, b):
 
 
 class _Ops:
-    """The primitive operations one iteration is built from (counted)."""
+    """The primitive operations one iteration is built from (counted).
 
-    def __init__(self, A, precond, counter):
+    ``summation`` picks the order in which u^H v = sum conj(u_i) v_i is
+    accumulated; the paper does not fix it.  "blas" (numpy's vdot) is the
+    default; "exact" rounds the sum of the rounded products once (math.fsum),
+    "reversed" sums from the last entry.  The alternatives exist to measure how
+    much an iteration depends on summation order alone.
+    """
+
+    def __init__(self, A, precond, counter, summation="blas"):
+        if summation not in ("blas", "exact", "reversed"):
+            raise ValueError("summation must be 'blas', 'exact' or 'reversed'")
         self.A = A
         self.precond = precond
         self.counter = counter
+        self.summation = summation
 
     def _c(self, key):
         if self.counter is not None:
@@ -104,7 +115,14 @@ class _Ops:
 
     def dot(self, u, v):
         self._c("dot")
-        return np.vdot(u, v)            # u^H v
+        if self.summation == "blas":
+            return np.vdot(u, v)        # u^H v
+        if self.summation == "reversed":
+            return np.vdot(u[::-1], v[::-1])
+        prod = np.conj(u) * v
+        if np.iscomplexobj(prod):
+            return complex(math.fsum(prod.real), math.fsum(prod.imag))
+        return math.fsum(prod)
 
     def saxpy(self, u, a, v):
         self._c("saxpy")
@@ -124,7 +142,7 @@ def _bad(z):
 
 
 def mlbicgstabt(A, b, Q, x0=None, tol=1e-10, maxit=1000, kappa=0.0, precond=None,
-                record_x=0, counter=None, observer=None, q_update=None):
+                record_x=0, counter=None, observer=None, q_update=None, summation="blas"):
     """Solve A x = b with ML(n)BiCGStabt; n is the number of columns of Q.
 
     A        : matrix-like supporting ``A @ v`` and ``A.conj().T`` (dense or scipy sparse)
@@ -132,6 +150,7 @@ def mlbicgstabt(A, b, Q, x0=None, tol=1e-10, maxit=1000, kappa=0.0, precond=None
     record_x : keep x_1 .. x_record_x in ``x_history``
     counter  : an OpCounter; ``counter.mark(('cycle', j))`` is recorded at the start of every cycle
     observer : callable(event, **state) called at a few points (for biorthogonality tests)
+    summation: order of the inner-product sums ("blas", "exact", "reversed"); see _Ops
     q_update : test hook realising adaptive shadow vectors (Section 3 FOM/GMRES relations):
                called as q_update(k, r_k) right after r_k is formed in cycle 0 (and with k = 0
                for r_0); a returned vector replaces q_{k+1} before it is first used.
@@ -146,7 +165,7 @@ def mlbicgstabt(A, b, Q, x0=None, tol=1e-10, maxit=1000, kappa=0.0, precond=None
     AH = A.conj().T
     if A_is_sparse:
         AH = AH.tocsr()
-    ops = _Ops(A, precond, counter)
+    ops = _Ops(A, precond, counter, summation)
 
     def apply_mh(v):     # M^{-H} v
         return v if precond is None else precond[1](v)

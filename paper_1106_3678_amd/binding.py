@@ -1,0 +1,229 @@
+"""ctypes binding of the C ABI declared in include/mlbicgstab.h.
+
+Argument marshalling only: every step of a solve runs in the HIP library.
+PyTorch supplies device memory and streams.  If the built library is missing
+this module raises at import time; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlbicgstab.so")
+
+MLB_CONVERGED, MLB_MAXIT, MLB_BREAKDOWN = 0, 1, -1
+MLB_EINVAL, MLB_ENOMEM, MLB_EHIP, MLB_EUNSUPPORTED = -2, -3, -4, -5
+MLB_R64, MLB_C128 = 0, 1
+MLB_CSR, MLB_BSR3 = 0, 1
+MLB_PREC_FP64, MLB_PREC_FP32_IR = 0, 1
+MLB_MAX_N = 32
+MLB_KERNEL_SPMV_STEP, MLB_KERNEL_ALPHA_STEP, MLB_KERNEL_COMBINE = 0, 1, 2
+
+
+class mlb_matrix(ctypes.Structure):
+    _fields_ = [
+        ("format", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("nrows", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col_idx", ctypes.c_void_p),
+        ("values", ctypes.c_void_p),
+    ]
+
+
+class mlb_options(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("maxit", ctypes.c_int64),
+        ("kappa", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("inner_tol", ctypes.c_double),
+        ("max_outer", ctypes.c_int32),
+        ("record_iterates", ctypes.c_int32),
+        ("iterates", ctypes.c_void_p),
+    ]
+
+
+class mlb_result(ctypes.Structure):
+    _fields_ = [
+        ("flag", ctypes.c_int32),
+        ("iter", ctypes.c_int64),
+        ("outer_iters", ctypes.c_int32),
+        ("fp64_iters", ctypes.c_int64),
+        ("err_recursive", ctypes.c_double),
+        ("err_true", ctypes.c_double),
+        ("setup_ms", ctypes.c_double),
+        ("solve_ms", ctypes.c_double),
+    ]
+
+
+mlb_handle = ctypes.c_void_p
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_lib.mlbicgstab_create.argtypes = [ctypes.POINTER(mlb_matrix), ctypes.POINTER(mlb_options), ctypes.c_void_p,
+                                   ctypes.POINTER(mlb_handle)]
+_lib.mlbicgstab_create.restype = ctypes.c_int
+_lib.mlbicgstab_workspace_size.argtypes = [ctypes.POINTER(mlb_matrix), ctypes.POINTER(mlb_options),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+_lib.mlbicgstab_workspace_size.restype = ctypes.c_int
+_lib.mlbicgstab_solve.argtypes = [mlb_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.POINTER(mlb_result)]
+_lib.mlbicgstab_solve.restype = ctypes.c_int
+_lib.mlbicgstab_destroy.argtypes = [mlb_handle]
+_lib.mlbicgstab_destroy.restype = ctypes.c_int
+_lib.mlbicgstab_last_error.argtypes = []
+_lib.mlbicgstab_last_error.restype = ctypes.c_char_p
+_lib.mlbicgstab_time_kernel.argtypes = [mlb_handle, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+_lib.mlbicgstab_time_kernel.restype = ctypes.c_int
+
+
+class MlbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mlbicgstab error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc <= -2:
+        raise MlbError(rc, mlbicgstab_last_error())
+    return rc
+
+
+# ---- the C entry points, same names ---------------------------------------------
+
+
+def mlbicgstab_create(A: mlb_matrix, opt: mlb_options, hip_stream: int = 0):
+    h = mlb_handle()
+    _check(_lib.mlbicgstab_create(ctypes.byref(A), ctypes.byref(opt), ctypes.c_void_p(hip_stream), ctypes.byref(h)))
+    return h
+
+
+def mlbicgstab_workspace_size(A: mlb_matrix, opt: mlb_options) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.mlbicgstab_workspace_size(ctypes.byref(A), ctypes.byref(opt), ctypes.byref(out)))
+    return out.value
+
+
+def mlbicgstab_solve(h, b_ptr: int, x_ptr: int, q_ptr: int, ldq: int) -> mlb_result:
+    res = mlb_result()
+    _check(_lib.mlbicgstab_solve(h, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), ctypes.c_void_p(q_ptr),
+                                 ctypes.c_int64(ldq), ctypes.byref(res)))
+    return res
+
+
+def mlbicgstab_destroy(h) -> int:
+    return _check(_lib.mlbicgstab_destroy(h))
+
+
+def mlbicgstab_last_error() -> str:
+    return _lib.mlbicgstab_last_error().decode()
+
+
+def mlbicgstab_time_kernel(h, kernel: int, reps: int) -> float:
+    ms = ctypes.c_double()
+    _check(_lib.mlbicgstab_time_kernel(h, kernel, reps, ctypes.byref(ms)))
+    return ms.value
+
+
+def raw_call(name, *args):
+    """The raw C function (for tests of the error paths)."""
+    return getattr(_lib, name)(*args)
+
+
+# ---- torch convenience layer (marshalling only) ----------------------------------
+
+
+@dataclass
+class DeviceMatrix:
+    """Device arrays of one sparse matrix (torch tensors) plus its descriptor."""
+    row_ptr: object
+    col_idx: object
+    values: object
+    nrows: int
+    fmt: int
+    dtype: int
+
+    def descriptor(self) -> mlb_matrix:
+        nnz = int(self.col_idx.numel())
+        return mlb_matrix(self.fmt, self.dtype, self.nrows, nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                          self.values.data_ptr())
+
+
+def to_device(A, device="cuda"):
+    """Upload a scipy CSR or BSR (3x3 blocks) matrix as int32 / float64 or complex128 tensors."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    if sp.isspmatrix_bsr(A) or isinstance(A, sp.bsr_array):
+        if A.blocksize != (3, 3):
+            raise ValueError("BSR matrices must have 3x3 blocks")
+        fmt = MLB_BSR3
+        vals = np.ascontiguousarray(A.data)
+    else:
+        A = A.tocsr()
+        fmt = MLB_CSR
+        vals = np.ascontiguousarray(A.data)
+    cplx = np.iscomplexobj(vals)
+    vals = vals.astype(np.complex128 if cplx else np.float64)
+    rp = torch.from_numpy(np.ascontiguousarray(A.indptr.astype(np.int32))).to(device)
+    ci = torch.from_numpy(np.ascontiguousarray(A.indices.astype(np.int32))).to(device)
+    v = torch.from_numpy(vals.reshape(-1)).to(device)
+    return DeviceMatrix(rp, ci, v, A.shape[0], fmt, MLB_C128 if cplx else MLB_R64)
+
+
+def column_major(Q, device="cuda"):
+    """An N x n torch tensor with column-major strides (1, N) holding Q."""
+    import numpy as np
+    import torch
+
+    Qf = np.asarray(Q)
+    t = torch.from_numpy(np.ascontiguousarray(Qf.T)).to(device)   # n x N row-major == N x n column-major
+    return t.t()
+
+
+class Solver:
+    """One handle: create() on construction, solve() per right-hand side, destroy() on close()."""
+
+    def __init__(self, dmat: DeviceMatrix, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
+                 precision: int = MLB_PREC_FP64, inner_tol: float = 0.0, max_outer: int = 0,
+                 record_iterates: int = 0, iterates=None, stream=None):
+        import torch
+
+        self.dmat = dmat
+        self.n = n
+        self.iterates = iterates
+        self.opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, max_outer, record_iterates,
+                               iterates.data_ptr() if iterates is not None else None)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = mlbicgstab_create(dmat.descriptor(), self.opt, self.stream.cuda_stream)
+
+    def solve(self, b, x, Q) -> mlb_result:
+        N = self.dmat.nrows
+        if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != self.n or Q.stride(0) != 1:
+            raise ValueError("Q must be an N x n column-major tensor")
+        if b.numel() != N or x.numel() != N or not x.is_contiguous() or not b.is_contiguous():
+            raise ValueError("b and x must be contiguous vectors of length N")
+        ldq = Q.stride(1) if self.n > 1 else N
+        return mlbicgstab_solve(self.h, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
+
+    def time_kernel(self, kernel: int, reps: int) -> float:
+        return mlbicgstab_time_kernel(self.h, kernel, reps)
+
+    def close(self):
+        if self.h:
+            mlbicgstab_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

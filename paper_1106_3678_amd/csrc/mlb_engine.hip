@@ -1,0 +1,798 @@
+// Host side of the ML(n)BiCGStab library: the C ABI of include/mlbicgstab.h,
+// the per-cycle launch schedule of Algorithm 7.1 (M = I), the construction of
+// A^H, and the fp32-inner / fp64-refinement driver.
+//
+// One Engine<V> owns the Krylov workspace for one value type V (fp64 or fp32,
+// real or complex).  Every step of the iteration is a kernel from
+// mlb_kernels.hpp; the host only enqueues them, cycle by cycle, and watches a
+// host-mapped "done" flag the device raises when the solve ends.  The host
+// stays at most two cycles ahead of the device, so the iteration never waits
+// for the host and the kernels of at most one cycle run after the end (they
+// return at once because the device flag is set).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mlbicgstab.h"
+#include "mlb_kernels.hpp"
+#include "mlb_transpose.hpp"
+
+namespace mlb {
+
+static thread_local std::string g_last_error;
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define HIP_TRY(call)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) throw Error{MLB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Device allocations owned by one solver, freed together.
+struct Allocs {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* get(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{MLB_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  ~Allocs() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+static int grid_for(long long work, int cap) {
+  long long g = (work + BLOCK - 1) / BLOCK;
+  if (g < 1) g = 1;
+  return (int)std::min<long long>(g, cap);
+}
+
+constexpr int MAX_GRID = 2048;      // workgroups of a streaming pass (8 per CU)
+
+// ------------------------------------------------------------------ matrices
+
+template <class V>
+struct Mat {
+  int format = MLB_CSR;
+  int nrows = 0;       // scalar rows
+  int nbrows = 0;      // rows of the index structure (block rows for BSR3)
+  long long nnz = 0;   // entries / blocks
+  const int* rp = nullptr;
+  const int* ci = nullptr;
+  const V* val = nullptr;
+  int lpr = 8;         // lanes per (block) row in the SpMV tile
+};
+
+static int pick_lpr(long long nnz, int nbrows) {
+  double mean = nbrows > 0 ? (double)nnz / nbrows : 1.0;
+  if (mean <= 4.0) return 4;
+  if (mean <= 8.0) return 8;
+  if (mean <= 16.0) return 16;
+  return 32;
+}
+
+// Checks row_ptr / col_idx of a user matrix on the device (so that no kernel
+// ever indexes outside the arrays the descriptor declares).
+__global__ void k_validate(const int* __restrict__ rp, const int* __restrict__ ci, int nbrows, long long nnz,
+                           int ncols, int* __restrict__ bad) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t <= nbrows; t += (long long)gridDim.x * blockDim.x) {
+    const int v = rp[t];
+    if (t == 0 && v != 0) atomicOr(bad, 1);
+    if (t == nbrows && (long long)v != nnz) atomicOr(bad, 2);
+    if (t < nbrows && rp[t + 1] < v) atomicOr(bad, 4);
+  }
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nnz; q += (long long)gridDim.x * blockDim.x) {
+    const int c = ci[q];
+    if (c < 0 || c >= ncols) atomicOr(bad, 8);
+  }
+}
+
+template <class V>
+static Mat<V> build_transpose(const Mat<V>& A, Allocs& al, hipStream_t s) {
+  Mat<V> T;
+  T.format = A.format;
+  T.nrows = A.nrows;
+  T.nbrows = A.nbrows;
+  T.nnz = A.nnz;
+  const int m = A.nbrows;
+  const int bs = A.format == MLB_BSR3 ? 9 : 1;
+  int* rpT = al.get<int>(m + 1);
+  int* ciT = al.get<int>(A.nnz);
+  V* valT = al.get<V>((size_t)A.nnz * bs);
+  Allocs tmp;
+  int* cnt = tmp.get<int>(m);
+  int* fill = tmp.get<int>(m);
+  HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int) * m, s));
+  HIP_TRY(hipMemsetAsync(fill, 0, sizeof(int) * m, s));
+  if (A.nnz > 0) k_col_count<<<grid_for(A.nnz, 4096), BLOCK, 0, s>>>(A.ci, A.nnz, cnt);
+  k_scan<<<1, SCAN_T, 0, s>>>(cnt, m, rpT);
+  if (bs == 1) {
+    k_scatter<V, 1><<<grid_for(m, 4096), BLOCK, 0, s>>>(A.rp, A.ci, A.val, m, rpT, fill, ciT, valT);
+    k_sort_rows<V, 1><<<grid_for(m, 4096), BLOCK, 0, s>>>(rpT, m, ciT, valT);
+  } else {
+    k_scatter<V, 9><<<grid_for(m, 4096), BLOCK, 0, s>>>(A.rp, A.ci, A.val, m, rpT, fill, ciT, valT);
+    k_sort_rows<V, 9><<<grid_for(m, 4096), BLOCK, 0, s>>>(rpT, m, ciT, valT);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));   // tmp is freed on return
+  T.rp = rpT;
+  T.ci = ciT;
+  T.val = valT;
+  T.lpr = pick_lpr(T.nnz, T.nbrows);
+  return T;
+}
+
+// ------------------------------------------------------------------ launch dispatch
+
+static int bucket(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
+
+template <class V, class Sc, int MODE, int ND>
+static void launch_spmv_nd(const Mat<V>& A, int grid, hipStream_t s, State<Sc>* st, Sc* part, const SpmvArgs<V>& a,
+                           int phase, int i, int j, int n, int flags) {
+#define MLB_SPMV_CASE(L)                                                                                     \
+  if (A.format == MLB_CSR)                                                                                   \
+    k_spmv<V, Sc, ND, L, 0, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);                \
+  else                                                                                                       \
+    k_spmv<V, Sc, ND, L, 1, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);
+#define MLB_SPMV_WCASE(L)                                                                                    \
+  if (A.format == MLB_CSR)                                                                                   \
+    k_spmv_csrw<V, Sc, ND, L, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, flags);                             \
+  else                                                                                                       \
+    k_spmv<V, Sc, ND, L, 1, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);
+  switch (A.lpr) {
+    case 4: MLB_SPMV_WCASE(4) break;
+    case 8: MLB_SPMV_WCASE(8) break;
+    case 16: MLB_SPMV_CASE(16) break;
+    default: MLB_SPMV_CASE(32) break;
+  }
+#undef MLB_SPMV_CASE
+#undef MLB_SPMV_WCASE
+}
+
+// Resets the device scalars before a solve.
+template <class Sc>
+__global__ void k_init_state(State<Sc>* st, double tol, long long maxit, double kappa, int* host_done) {
+  st->done = 0;
+  st->flag = 1;
+  st->iter = 0;
+  st->maxit = maxit;
+  st->tol = tol;
+  st->kappa = kappa;
+  st->bnrm2 = 1.0;
+  st->err = 0.0;
+  st->uu = 0.0;
+  st->e = st->alpha = zero<Sc>();
+  st->omega = from_real<Sc>(1.0);
+  for (int q = 0; q < NMAX; ++q) st->c[q] = st->t[q] = st->tg[q] = st->beta[q] = zero<Sc>();
+  for (int q = 0; q < NMAX * NMAX; ++q) st->S[q] = zero<Sc>();
+  for (int q = 0; q < 8; ++q) st->aux[q] = zero<Sc>();
+  st->host_done = host_done;
+}
+
+
+// ------------------------------------------------------------------ engine
+
+template <class V>
+struct Engine {
+  using Sc = typename traits<V>::wide;
+  int N = 0, n = 0, nb = 4;
+  Mat<V> A, AH;
+  V *G = nullptr, *W = nullptr, *F = nullptr, *r = nullptr, *gt = nullptr, *z = nullptr;
+  State<Sc>* st = nullptr;
+  Sc* part = nullptr;
+  int grid_vec = 1, grid_spmv = 1;
+  hipStream_t s = nullptr;
+  int* host_done = nullptr;       // pinned, mapped
+  int* host_done_dev = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // per solve
+  const V* Q = nullptr;
+  long long ldq = 0;
+
+  void init(const Mat<V>& A_, const Mat<V>& AH_, int n_, hipStream_t s_, Allocs& al) {
+    A = A_;
+    AH = AH_;
+    N = A.nrows;
+    n = n_;
+    nb = bucket(n);
+    s = s_;
+    const size_t Nn = (size_t)N * n;
+    G = al.get<V>(Nn);
+    W = al.get<V>(Nn);
+    F = al.get<V>((size_t)N * std::max(n - 1, 1));
+    r = al.get<V>(N);
+    gt = al.get<V>(N);
+    z = al.get<V>(N);
+    st = al.get<State<Sc>>(1);
+    grid_vec = grid_for(N, MAX_GRID);
+    grid_spmv = grid_for(A.nbrows, MAX_GRID);
+    part = al.get<Sc>((size_t)std::max(grid_vec, grid_spmv) * (NMAX + 1));
+    HIP_TRY(hipHostMalloc((void**)&host_done, sizeof(int), hipHostMallocMapped));
+    *host_done = 0;
+    HIP_TRY(hipHostGetDevicePointer((void**)&host_done_dev, host_done, 0));
+    for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  void release() {
+    if (host_done) (void)hipHostFree(host_done);
+    host_done = nullptr;
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+
+  static size_t bytes(int N, int n, long long grid) {
+    return sizeof(V) * ((size_t)N * (2 * n + std::max(n - 1, 1) + 3)) + sizeof(State<Sc>) +
+           sizeof(Sc) * (size_t)grid * (NMAX + 1);
+  }
+
+  // ---- single launches --------------------------------------------------
+
+  // Sum the partials of the pass just launched and run the recurrence of `phase`.
+  void scalar(int nblocks, int stride, int nsum, int phase, int i, int j) {
+    switch (stride) {
+      case 4: k_scalar<Sc, 4><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+      case 5: k_scalar<Sc, 5><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+      case 8: k_scalar<Sc, 8><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+      case 9: k_scalar<Sc, 9><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+      case 16: k_scalar<Sc, 16><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+      case 17: k_scalar<Sc, 17><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+      case 32: k_scalar<Sc, 32><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+      default: k_scalar<Sc, 33><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+    }
+  }
+
+  void spmv_resid(const Mat<V>& M, const V* xin, const V* b, V* out, const V* Qc, int phase, int flags = 0) {
+    SpmvArgs<V> a{};
+    a.format = M.format; a.nrows = M.nrows; a.nbrows = M.nbrows; a.rp = M.rp; a.ci = M.ci; a.val = M.val;
+    a.xin = xin; a.out1 = out; a.b = b; a.Q = Qc; a.nd = Qc ? 1 : 0;
+    launch_spmv_nd<V, Sc, SM_RESID, 4>(M, grid_spmv, s, st, part, a, phase, 0, 0, n, flags);
+    if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, 4, 3, phase, 0, 0);
+  }
+  void spmv_plain(const Mat<V>& M, const V* xin, V* out) {
+    SpmvArgs<V> a{};
+    a.format = M.format; a.nrows = M.nrows; a.nbrows = M.nbrows; a.rp = M.rp; a.ci = M.ci; a.val = M.val;
+    a.xin = xin; a.out1 = out;
+    launch_spmv_nd<V, Sc, SM_PLAIN, 4>(M, grid_spmv, s, st, part, a, PH_NONE, 0, 0, n, 0);
+  }
+  void spmv_omega(const V* u, V* zout) {
+    SpmvArgs<V> a{};
+    a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
+    a.xin = u; a.out1 = zout;
+    launch_spmv_nd<V, Sc, SM_OMEGA, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_OMEGA, 0, 0, n, 0);
+    scalar(grid_spmv, 4, 2, PH_SPMV_OMEGA, 0, 0);
+  }
+  // G_i = g + sum_{s<i} beta_s G_s (beta from the last PH_COMBINE)
+  void gcomb(const V* gin, int i, int flags = 0) {
+    k_gcomb<V, Sc><<<grid_vec, BLOCK, 0, s>>>(st, N, gin, G, N, i, G + (size_t)i * N, flags);
+  }
+  // w_i = A G_i ; S[s][i] = q_s^H w_i, s = i..n-1.  With gin != G_i the input is
+  // also copied to G_i (cycle close and set-up, where g_k = g).
+  void spmv_step(const V* gin, int i, int flags = 0) {
+    SpmvArgs<V> a{};
+    a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
+    V* Gi = G + (size_t)i * N;
+    a.xin = gin; a.out1 = W + (size_t)i * N; a.out2 = gin == Gi ? nullptr : Gi;
+    a.Q = Q; a.ldq = ldq; a.d0 = i; a.nd = n - i;
+    switch (nb) {
+      case 4: launch_spmv_nd<V, Sc, SM_STEP, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
+      case 8: launch_spmv_nd<V, Sc, SM_STEP, 8>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
+      case 16: launch_spmv_nd<V, Sc, SM_STEP, 16>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
+      default: launch_spmv_nd<V, Sc, SM_STEP, 32>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
+    }
+    if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, std::max(nb, 3), n - i, PH_SPMV_STEP, i, 0);
+  }
+  void alpha(V* x, int i_prev, int d0, int nd, int phase, int i, int j, V* xrec, long long K, int flags = 0) {
+    const V* gh = G + (size_t)i_prev * N;
+    const V* w = W + (size_t)i_prev * N;
+#define MLB_ALPHA(B) \
+  k_alpha<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, gh, r, w, Q, ldq, d0, nd, xrec, K, phase, i, j, n, flags)
+    switch (nb) {
+      case 4: MLB_ALPHA(4); break;
+      case 8: MLB_ALPHA(8); break;
+      case 16: MLB_ALPHA(16); break;
+      default: MLB_ALPHA(32); break;
+    }
+#undef MLB_ALPHA
+    if (!(flags & F_SKIP_SCALAR)) scalar(grid_vec, nb + 1, nd + 1, phase, i, j);
+  }
+  void combine(int t0, int t1, int nf, int i, int j, int flags = 0) {
+#define MLB_COMB(B)                                                                                            \
+  k_combine<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, r, W, G, N, t0, t1, gt, F, N, nf, PH_COMBINE, i, j, n, \
+                                                 flags)
+    switch (nb) {
+      case 4: MLB_COMB(4); break;
+      case 8: MLB_COMB(8); break;
+      case 16: MLB_COMB(16); break;
+      default: MLB_COMB(32); break;
+    }
+#undef MLB_COMB
+    if (!(flags & F_SKIP_SCALAR) && nf > 0) scalar(grid_vec, nb, nf, PH_COMBINE, i, j);
+  }
+  void omega_update(V* x, V* xrec, long long K) {
+#define MLB_OM(B) k_omega<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, r, z, Q, ldq, n, xrec, K, PH_OMEGA_UPD, n, 0)
+    switch (nb) {
+      case 4: MLB_OM(4); break;
+      case 8: MLB_OM(8); break;
+      case 16: MLB_OM(16); break;
+      default: MLB_OM(32); break;
+    }
+#undef MLB_OM
+    scalar(grid_vec, nb + 1, n + 1, PH_OMEGA_UPD, 0, 1);
+  }
+
+  // ---- the iteration ----------------------------------------------------
+
+  // Steps k = jn+1 .. jn+n of cycle j (Algorithm 7.1, i/j form).
+  void cycle(int j, V* x, V* xrec, long long K) {
+    for (int i = 1; i < n; ++i) {
+      // x_{jn+i} = x + alpha g ; r_{jn+i} = r - alpha w ; e = q_{i+1}^H r (and q_s^H r, s > i, when j >= 1)
+      alpha(x, i - 1, i, j >= 1 ? n - i : 1, PH_INNER, i, j, xrec, K);
+      // g = z_w - g/omega from the previous cycle's columns (j >= 1), or g = r (j = 0); f_s^H g, s < i
+      if (j >= 1) combine(i, n, i, i, j);
+      else combine(i, i, i, i, j);
+      // g_{jn+i} = g + sum beta_s g_s ; w_{jn+i} = A g_{jn+i} ; c and S column i
+      gcomb(gt, i);
+      spmv_step(G + (size_t)i * N, i);
+    }
+    // k = jn + n: half step to u, minimisation step, cycle close
+    alpha(x, n - 1, 0, 0, PH_HALF, n, j, xrec, K);
+    spmv_omega(r, z);
+    omega_update(x, xrec, K);
+    combine(0, n, 0, 0, j);
+    spmv_step(gt, 0);
+  }
+
+  struct Out {
+    int flag;
+    long long iter;
+    double err;
+    float setup_ms;
+  };
+
+  // Algorithm 7.1 with M = I from x (in: x_0, out: solution).
+  Out solve(const V* b, V* x, const V* Q_, long long ldq_, double tol, long long maxit, double kappa, V* xrec,
+            long long K) {
+    Q = Q_;
+    ldq = ldq_;
+    *(volatile int*)host_done = 0;
+    hipEvent_t t0, t1;
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    HIP_TRY(hipEventRecord(t0, s));
+    k_init_state<Sc><<<1, 1, 0, s>>>(st, tol, maxit, kappa, host_done_dev);
+    // r_0 = b - A x_0, ||b||, e_0 = q_1^H r_0, early exit
+    spmv_resid(A, x, b, r, Q, PH_SETUP);
+    // f_s = A^H q_s, s = 1..n-1
+    for (int c = 0; c + 1 < n; ++c) spmv_plain(AH, Q + (size_t)c * ldq, F + (size_t)c * N);
+    // g_0 = r_0, w_0 = A g_0, c_0 (and S column 0), alpha_1 = e_0 / c_0
+    spmv_step(r, 0);
+    HIP_TRY(hipEventRecord(t1, s));
+    HIP_TRY(hipGetLastError());
+    const long long max_cycles = maxit / n + 2;
+    for (long long j = 0; j <= max_cycles; ++j) {
+      cycle((int)std::min<long long>(j, 1), x, xrec, K);
+      HIP_TRY(hipEventRecord(ev[j & 1], s));
+      if (j >= 1) {
+        HIP_TRY(hipEventSynchronize(ev[(j - 1) & 1]));
+        if (*(volatile int*)host_done) break;
+      }
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    Out o{};
+    State<Sc> h;
+    HIP_TRY(hipMemcpy(&h, st, sizeof(State<Sc>), hipMemcpyDeviceToHost));
+    o.flag = h.done ? h.flag : 1;
+    o.iter = h.iter;
+    o.err = h.err;
+    HIP_TRY(hipEventElapsedTime(&o.setup_ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return o;
+  }
+
+  // ||b - A x|| and ||b|| in this engine's precision (sums left in st->aux).
+  void resid_sums(const V* b, const V* x, V* out) {
+    k_init_state<Sc><<<1, 1, 0, s>>>(st, 1.0, 1, 0.0, nullptr);
+    spmv_resid(A, x, b, out, nullptr, PH_NONE);
+  }
+  void read_aux(double* rr, double* bb) {
+    State<Sc> h;
+    HIP_TRY(hipMemcpyAsync(&h, st, sizeof(State<Sc>), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *rr = re(h.aux[0]);
+    *bb = re(h.aux[1]);
+  }
+};
+
+// ------------------------------------------------------------------ solver object
+
+template <class V64, class V32>
+struct Impl {
+  Engine<V64> e64;
+  Engine<V32> e32;
+  bool has32 = false;
+  V32* b32 = nullptr;   // scaled residual (inner right-hand side)
+  V32* x32 = nullptr;   // inner solution
+  V32* Q32 = nullptr;   // fp32 shadow block (ld = N)
+  V64* r64 = nullptr;   // fp64 residual b - A x
+  void release() {
+    e64.release();
+    if (has32) e32.release();
+  }
+};
+
+}  // namespace mlb
+
+using namespace mlb;
+
+struct mlb_solver {
+  int dtype = MLB_R64, format = MLB_CSR;
+  int N = 0;
+  mlb_options opt{};
+  hipStream_t s = nullptr;
+  bool own_stream = false;
+  bool solved = false;
+  Allocs al;
+  std::unique_ptr<Impl<double, float>> real;
+  std::unique_ptr<Impl<cplx<double>, cplx<float>>> cpx;
+  ~mlb_solver() {
+    if (real) real->release();
+    if (cpx) cpx->release();
+    if (own_stream && s) (void)hipStreamDestroy(s);
+  }
+};
+
+namespace mlb {
+
+static void check_options(const mlb_options* opt) {
+  if (!opt) throw Error{MLB_EINVAL, "options pointer is NULL"};
+  if (opt->n < 1) throw Error{MLB_EINVAL, "n must be >= 1"};
+  if (opt->n > MLB_MAX_N) throw Error{MLB_EUNSUPPORTED, "n > MLB_MAX_N (32) is not supported"};
+  if (!(opt->tol > 0.0) || !std::isfinite(opt->tol)) throw Error{MLB_EINVAL, "tol must be a finite positive number"};
+  if (opt->maxit < 1) throw Error{MLB_EINVAL, "maxit must be >= 1"};
+  if (!(opt->kappa >= 0.0) || !std::isfinite(opt->kappa)) throw Error{MLB_EINVAL, "kappa must be finite and >= 0"};
+  if (opt->precision != MLB_PREC_FP64 && opt->precision != MLB_PREC_FP32_IR)
+    throw Error{MLB_EINVAL, "precision must be MLB_PREC_FP64 or MLB_PREC_FP32_IR"};
+  if (opt->record_iterates < 0) throw Error{MLB_EINVAL, "record_iterates must be >= 0"};
+  if (opt->record_iterates > 0) {
+    if (!opt->iterates) throw Error{MLB_EINVAL, "record_iterates > 0 needs an iterates buffer"};
+    if (opt->precision != MLB_PREC_FP64) throw Error{MLB_EINVAL, "iterates are recorded by the fp64 iteration only"};
+    if (opt->record_iterates > opt->maxit) throw Error{MLB_EINVAL, "record_iterates must be <= maxit"};
+  }
+}
+
+static void check_matrix(const mlb_matrix* A) {
+  if (!A) throw Error{MLB_EINVAL, "matrix pointer is NULL"};
+  if (A->format != MLB_CSR && A->format != MLB_BSR3) throw Error{MLB_EINVAL, "format must be MLB_CSR or MLB_BSR3"};
+  if (A->dtype != MLB_R64 && A->dtype != MLB_C128) throw Error{MLB_EINVAL, "dtype must be MLB_R64 or MLB_C128"};
+  if (A->nrows < 1 || A->nrows > 0x7fffffffLL) throw Error{MLB_EINVAL, "nrows must be in [1, 2^31)"};
+  if (A->format == MLB_BSR3 && A->nrows % 3 != 0) throw Error{MLB_EINVAL, "BSR3 needs nrows divisible by 3"};
+  if (A->nnz < 0 || A->nnz > 0x7fffffffLL) throw Error{MLB_EINVAL, "nnz must be in [0, 2^31)"};
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values)))
+    throw Error{MLB_EINVAL, "row_ptr, col_idx and values must be device pointers"};
+}
+
+template <class V>
+static Mat<V> user_matrix(const mlb_matrix* A) {
+  Mat<V> M;
+  M.format = A->format;
+  M.nrows = (int)A->nrows;
+  M.nbrows = A->format == MLB_BSR3 ? (int)(A->nrows / 3) : (int)A->nrows;
+  M.nnz = A->nnz;
+  M.rp = A->row_ptr;
+  M.ci = A->col_idx;
+  M.val = (const V*)A->values;
+  M.lpr = pick_lpr(M.nnz, M.nbrows);
+  return M;
+}
+
+template <class V64, class V32>
+static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& im) {
+  Mat<V64> A = user_matrix<V64>(Adesc);
+  Mat<V64> AH = build_transpose(A, h->al, h->s);
+  im.e64.init(A, AH, h->opt.n, h->s, h->al);
+  im.r64 = h->al.get<V64>(h->N);
+  if (h->opt.precision == MLB_PREC_FP32_IR) {
+    const int bs = A.format == MLB_BSR3 ? 9 : 1;
+    Mat<V32> A32, AH32;
+    A32.format = AH32.format = A.format;
+    A32.nrows = AH32.nrows = A.nrows;
+    A32.nbrows = AH32.nbrows = A.nbrows;
+    A32.nnz = AH32.nnz = A.nnz;
+    A32.rp = A.rp;
+    A32.ci = A.ci;
+    AH32.rp = AH.rp;
+    AH32.ci = AH.ci;
+    V32* v = h->al.get<V32>((size_t)A.nnz * bs);
+    V32* vt = h->al.get<V32>((size_t)A.nnz * bs);
+    const long long m = (long long)A.nnz * bs;
+    if (m > 0) {
+      k_narrow<V32, V64><<<grid_for(m, 4096), BLOCK, 0, h->s>>>(v, A.val, m);
+      k_narrow<V32, V64><<<grid_for(m, 4096), BLOCK, 0, h->s>>>(vt, AH.val, m);
+    }
+    A32.val = v;
+    AH32.val = vt;
+    A32.lpr = A.lpr;
+    AH32.lpr = AH.lpr;
+    im.e32.init(A32, AH32, h->opt.n, h->s, h->al);
+    im.has32 = true;
+    im.b32 = h->al.get<V32>(h->N);
+    im.x32 = h->al.get<V32>(h->N);
+    im.Q32 = h->al.get<V32>((size_t)h->N * h->opt.n);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(h->s));
+}
+
+template <class V64, class V32>
+static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, const V64* Q, long long ldq,
+                      mlb_result* res) {
+  const mlb_options& o = h->opt;
+  const int N = h->N;
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  HIP_TRY(hipEventRecord(t0, h->s));
+  mlb_result R{};
+  int flag = 1;
+  if (o.precision == MLB_PREC_FP64) {
+    auto out = im.e64.solve(b, x, Q, ldq, o.tol, o.maxit, o.kappa, (V64*)o.iterates, o.record_iterates);
+    flag = out.flag;
+    R.iter = out.iter;
+    R.fp64_iters = out.iter;
+    R.err_recursive = out.err;
+    R.setup_ms = out.setup_ms;
+  } else {
+    // fp32 inner iteration inside fp64 iterative refinement
+    auto& e32 = im.e32;
+    for (int c = 0; c < o.n; ++c)
+      k_cast<V32, V64, typename traits<V64>::wide><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(
+          im.Q32 + (size_t)c * N, Q + (size_t)c * ldq, N, im.e64.st, 0);
+    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    const int max_outer = o.max_outer > 0 ? o.max_outer : 30;
+    long long used = 0;
+    double prev = INFINITY;
+    bool fallback = false;
+    int outer = 0;
+    flag = 1;
+    while (true) {
+      im.e64.resid_sums(b, x, im.r64);
+      double rr, bb;
+      im.e64.read_aux(&rr, &bb);
+      const double bn = bb > 0 ? std::sqrt(bb) : 1.0;
+      const double et = std::sqrt(rr) / bn;
+      R.err_true = et;
+      if (!std::isfinite(et)) { flag = -1; break; }
+      if (et < o.tol) { flag = 0; break; }
+      if (outer >= max_outer || used >= o.maxit) { flag = 1; break; }
+      if (outer >= 1 && et > 0.1 * prev) { fallback = true; break; }
+      prev = et;
+      ++outer;
+      // right-hand side r / ||r|| in fp32, zero initial guess
+      k_cast<V32, V64, typename traits<V64>::wide><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(im.b32, im.r64, N,
+                                                                                          im.e64.st, 1);
+      k_fill<V32><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(im.x32, N, zero<V32>());
+      auto io = e32.solve(im.b32, im.x32, im.Q32, N, inner_tol, o.maxit - used, o.kappa, nullptr, 0);
+      used += io.iter;
+      if (outer == 1) R.setup_ms = io.setup_ms;
+      if (io.flag == -1) { fallback = true; break; }
+      // x += ||r|| d
+      k_axpy_wide<V64, V32, typename traits<V64>::wide><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(x, im.x32, N,
+                                                                                             im.e64.st);
+      HIP_TRY(hipGetLastError());
+    }
+    R.outer_iters = outer;
+    R.iter = used;
+    if (fallback) {
+      long long left = std::max<long long>(1, o.maxit - used);
+      auto out = im.e64.solve(b, x, Q, ldq, o.tol, left, o.kappa, nullptr, 0);
+      flag = out.flag;
+      R.fp64_iters = out.iter;
+      R.iter = used + out.iter;
+      R.err_recursive = out.err;
+    }
+  }
+  // true residual ||b - A x|| / ||b|| in fp64
+  im.e64.resid_sums(b, x, im.r64);
+  double rr, bb;
+  im.e64.read_aux(&rr, &bb);
+  R.err_true = std::sqrt(rr) / (bb > 0 ? std::sqrt(bb) : 1.0);
+  if (o.precision == MLB_PREC_FP32_IR && R.fp64_iters == 0) R.err_recursive = R.err_true;
+  HIP_TRY(hipEventRecord(t1, h->s));
+  HIP_TRY(hipEventSynchronize(t1));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+  R.solve_ms = ms;
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  R.flag = flag;
+  if (res) *res = R;
+  return flag;
+}
+
+template <class V>
+static double time_kernel_impl(Engine<V>& e, int kernel, int reps) {
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  const int fl = F_IGNORE_DONE | F_SKIP_SCALAR;
+  long long launches = 0;
+  auto one_round = [&]() {
+    if (kernel == MLB_KERNEL_SPMV_STEP) {
+      for (int i = 0; i < e.n; ++i, ++launches) e.spmv_step(i == 0 ? e.gt : e.G + (size_t)i * e.N, i, fl);
+    } else if (kernel == MLB_KERNEL_ALPHA_STEP) {
+      for (int i = 1; i <= e.n; ++i, ++launches)
+        e.alpha(e.z, i - 1, i % e.n, i < e.n ? e.n - i : 0, PH_INNER, i, 1, nullptr, 0, fl);
+    } else {
+      for (int i = 0; i < e.n; ++i, ++launches) e.combine(i, e.n, i, i, 1, fl);
+    }
+  };
+  one_round();   // warm-up
+  launches = 0;
+  HIP_TRY(hipEventRecord(t0, e.s));
+  for (int r = 0; r < reps; ++r) one_round();
+  HIP_TRY(hipEventRecord(t1, e.s));
+  HIP_TRY(hipEventSynchronize(t1));
+  HIP_TRY(hipGetLastError());
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return launches > 0 ? ms / launches : 0.0;
+}
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return MLB_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MLB_EHIP;
+  }
+}
+
+}  // namespace mlb
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int mlbicgstab_workspace_size(const mlb_matrix* A, const mlb_options* opt, size_t* bytes) {
+  return guarded([&]() -> int {
+    check_matrix(A);
+    check_options(opt);
+    if (!bytes) throw Error{MLB_EINVAL, "bytes pointer is NULL"};
+    const int N = (int)A->nrows;
+    const int nbr = A->format == MLB_BSR3 ? N / 3 : N;
+    const int bs = A->format == MLB_BSR3 ? 9 : 1;
+    const long long grid = std::max(grid_for(N, MAX_GRID), grid_for(nbr, MAX_GRID));
+    const bool c = A->dtype == MLB_C128;
+    const size_t sv = c ? 16 : 8;
+    size_t t = (size_t)(nbr + 1) * 4 + (size_t)A->nnz * 4 + (size_t)A->nnz * bs * sv;   // A^H
+    t += c ? Engine<cplx<double>>::bytes(N, opt->n, grid) : Engine<double>::bytes(N, opt->n, grid);
+    t += (size_t)N * sv;                                                                   // r64
+    if (opt->precision == MLB_PREC_FP32_IR) {
+      t += (size_t)A->nnz * bs * sv;                                                       // fp32 A, A^H values
+      t += c ? Engine<cplx<float>>::bytes(N, opt->n, grid) : Engine<float>::bytes(N, opt->n, grid);
+      t += (size_t)N * (2 + opt->n) * (sv / 2);
+    }
+    *bytes = t;
+    return 0;
+  });
+}
+
+int mlbicgstab_create(const mlb_matrix* A, const mlb_options* opt, void* hip_stream, mlb_handle* out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> int {
+    if (!out) throw Error{MLB_EINVAL, "out pointer is NULL"};
+    check_matrix(A);
+    check_options(opt);
+    auto h = std::make_unique<mlb_solver>();
+    h->dtype = A->dtype;
+    h->format = A->format;
+    h->N = (int)A->nrows;
+    h->opt = *opt;
+    if (hip_stream) {
+      h->s = (hipStream_t)hip_stream;
+    } else {
+      HIP_TRY(hipStreamCreateWithFlags(&h->s, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+    // validate the index arrays on the device before any kernel relies on them
+    {
+      Allocs tmp;
+      int* bad = tmp.get<int>(1);
+      HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), h->s));
+      const int nbr = A->format == MLB_BSR3 ? (int)(A->nrows / 3) : (int)A->nrows;
+      k_validate<<<grid_for(std::max<long long>(nbr + 1, A->nnz), 4096), BLOCK, 0, h->s>>>(
+          A->row_ptr, A->col_idx, nbr, A->nnz, nbr, bad);
+      HIP_TRY(hipGetLastError());
+      int hb = 0;
+      HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->s));
+      HIP_TRY(hipStreamSynchronize(h->s));
+      if (hb) {
+        std::string why;
+        if (hb & 1) why += " row_ptr[0] != 0;";
+        if (hb & 2) why += " row_ptr[last] != nnz;";
+        if (hb & 4) why += " row_ptr decreases;";
+        if (hb & 8) why += " col_idx out of range;";
+        throw Error{MLB_EINVAL, "invalid matrix:" + why};
+      }
+    }
+    if (A->dtype == MLB_R64) {
+      h->real = std::make_unique<Impl<double, float>>();
+      create_impl(h.get(), A, *h->real);
+    } else {
+      h->cpx = std::make_unique<Impl<cplx<double>, cplx<float>>>();
+      create_impl(h.get(), A, *h->cpx);
+    }
+    *out = h.release();
+    return 0;
+  });
+}
+
+int mlbicgstab_solve(mlb_handle h, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res) {
+  return guarded([&]() -> int {
+    if (!h) throw Error{MLB_EINVAL, "handle is NULL"};
+    if (!b || !x || !Q) throw Error{MLB_EINVAL, "b, x and Q must be device pointers"};
+    if (ldq < h->N) throw Error{MLB_EINVAL, "ldq must be >= N"};
+    int rc;
+    if (h->real)
+      rc = solve_impl(h, *h->real, (const double*)b, (double*)x, (const double*)Q, ldq, res);
+    else
+      rc = solve_impl(h, *h->cpx, (const cplx<double>*)b, (cplx<double>*)x, (const cplx<double>*)Q, ldq, res);
+    h->solved = true;
+    return rc;
+  });
+}
+
+int mlbicgstab_destroy(mlb_handle h) {
+  return guarded([&]() -> int {
+    if (!h) return 0;
+    (void)hipStreamSynchronize(h->s);
+    delete h;
+    return 0;
+  });
+}
+
+const char* mlbicgstab_last_error(void) { return g_last_error.c_str(); }
+
+int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* ms_per_launch) {
+  return guarded([&]() -> int {
+    if (!h || !ms_per_launch) throw Error{MLB_EINVAL, "handle and ms_per_launch must be non-NULL"};
+    if (!h->solved) throw Error{MLB_EINVAL, "time_kernel needs a prior solve"};
+    if (kernel < MLB_KERNEL_SPMV_STEP || kernel > MLB_KERNEL_COMBINE) throw Error{MLB_EINVAL, "unknown kernel"};
+    if (reps < 1) throw Error{MLB_EINVAL, "reps must be >= 1"};
+    const bool ir = h->opt.precision == MLB_PREC_FP32_IR;
+    if (h->real)
+      *ms_per_launch = ir ? time_kernel_impl(h->real->e32, kernel, reps) : time_kernel_impl(h->real->e64, kernel, reps);
+    else
+      *ms_per_launch = ir ? time_kernel_impl(h->cpx->e32, kernel, reps) : time_kernel_impl(h->cpx->e64, kernel, reps);
+    return 0;
+  });
+}
+
+}  // extern "C"

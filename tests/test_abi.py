@@ -1,0 +1,95 @@
+"""The C ABI: the library loads, exports every entry point the header declares, and rejects bad
+arguments before touching a GPU (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlbicgstab.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlbicgstab_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def binding():
+    from paper_1106_3678_amd import lib_built
+
+    if not lib_built():
+        pytest.fail("libmlbicgstab.so is not built (run __graft_entry__.build())")
+    from paper_1106_3678_amd import binding as b
+    return b
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("mlbicgstab_create", "mlbicgstab_solve", "mlbicgstab_destroy", "mlbicgstab_workspace_size",
+              "mlbicgstab_last_error", "mlbicgstab_time_kernel"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(binding):
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _desc(binding, **kw):
+    d = dict(format=binding.MLB_CSR, dtype=binding.MLB_R64, nrows=10, nnz=10, row_ptr=1, col_idx=1, values=1)
+    d.update(kw)
+    return binding.mlb_matrix(**d)
+
+
+def _opt(binding, **kw):
+    o = dict(n=4, tol=1e-10, maxit=100, kappa=0.0, precision=0, inner_tol=0.0, max_outer=0, record_iterates=0,
+             iterates=None)
+    o.update(kw)
+    return binding.mlb_options(**o)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(m=dict(format=7)), dict(m=dict(dtype=9)), dict(m=dict(nrows=0)), dict(m=dict(nrows=10, format=1)),
+    dict(m=dict(nnz=-1)), dict(m=dict(row_ptr=None)),
+    dict(o=dict(n=0)), dict(o=dict(tol=0.0)), dict(o=dict(tol=float("nan"))), dict(o=dict(maxit=0)),
+    dict(o=dict(kappa=-1.0)), dict(o=dict(precision=5)), dict(o=dict(record_iterates=3)),
+])
+def test_create_rejects_bad_arguments(binding, bad):
+    A = _desc(binding, **bad.get("m", {}))
+    o = _opt(binding, **bad.get("o", {}))
+    h = binding.mlb_handle()
+    rc = binding.raw_call("mlbicgstab_create", ctypes.byref(A), ctypes.byref(o), None, ctypes.byref(h))
+    assert rc == binding.MLB_EINVAL
+    assert h.value is None
+    assert binding.mlbicgstab_last_error() != ""
+
+
+def test_n_above_max_is_unsupported(binding):
+    A = _desc(binding)
+    o = _opt(binding, n=33)
+    h = binding.mlb_handle()
+    rc = binding.raw_call("mlbicgstab_create", ctypes.byref(A), ctypes.byref(o), None, ctypes.byref(h))
+    assert rc == binding.MLB_EUNSUPPORTED
+
+
+def test_null_handle_paths(binding):
+    res = binding.mlb_result()
+    assert binding.raw_call("mlbicgstab_solve", None, None, None, None, ctypes.c_int64(1),
+                            ctypes.byref(res)) == binding.MLB_EINVAL
+    assert binding.raw_call("mlbicgstab_destroy", None) == 0
+    ms = ctypes.c_double()
+    assert binding.raw_call("mlbicgstab_time_kernel", None, 0, 1, ctypes.byref(ms)) == binding.MLB_EINVAL
+
+
+def test_workspace_size_model(binding):
+    """(4n+4)N-type footprint: grows linearly in n and N (Table 4.3 storage)."""
+    s1 = binding.mlbicgstab_workspace_size(_desc(binding, nrows=30000, nnz=150000), _opt(binding, n=4))
+    s2 = binding.mlbicgstab_workspace_size(_desc(binding, nrows=30000, nnz=150000), _opt(binding, n=8))
+    s3 = binding.mlbicgstab_workspace_size(_desc(binding, nrows=60000, nnz=300000), _opt(binding, n=4))
+    assert s2 > s1 and s3 > 1.9 * s1
+    # 3 vectors (G, W, F) per extra shadow vector, 8 bytes each
+    assert abs((s2 - s1) - 4 * 3 * 30000 * 8) < 1024

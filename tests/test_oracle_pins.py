@@ -351,3 +351,14 @@ def test_sample_execution_section_7():
     assert res.flag in (0, 1, -1)
     if res.flag == 0:
         assert true_error(A, res.x, b) < 1e-5
+
+
+@pytest.mark.parametrize("summation", ["exact", "reversed"])
+def test_summation_order_option(summation):
+    """Other summation orders of u^H v give the same solve on a well-conditioned system."""
+    p = workloads.config1(n=4)
+    a = mlbicgstabt(p.A, p.b, p.Q, tol=p.tol, maxit=p.maxit, record_x=10)
+    b = mlbicgstabt(p.A, p.b, p.Q, tol=p.tol, maxit=p.maxit, record_x=10, summation=summation)
+    assert a.flag == b.flag == 0 and abs(a.iter - b.iter) <= 1
+    for k in range(10):
+        assert np.linalg.norm(a.x_history[k] - b.x_history[k]) < 1e-10 * np.linalg.norm(a.x_history[k])

@@ -140,14 +140,19 @@ def convdiff_3d(m: int, pe: float, gen: np.random.Generator | None = None, sigma
     return _stencil_csr((m, m, m), vel, nu=nu, shift=shift, dtype=dtype)
 
 
-def helmholtz_3d(m: int, pe: float, k: float, gen: np.random.Generator, sigma: float = 8.0):
+def helmholtz_3d(m: int, pe: float, k: float, gen: np.random.Generator, sigma: float = 8.0,
+                 velocity: str = "constant"):
     """Complex shifted Laplacian with upwind convection, h^2-scaled.
 
-    A = L + C - (k h)^2 (1 - 0.5 i) I : complex non-Hermitian.
+    A = L + C - (k h)^2 (1 - 0.5 i) I : complex non-Hermitian.  The convection
+    has uniform speed along a seeded direction (velocity="smooth": a smooth
+    seeded direction field).
     """
     h = 1.0 / (m + 1)
     shift = -((k * h) ** 2) * (1.0 - 0.5j)
-    return convdiff_3d(m, pe, gen=gen, sigma=sigma, shift=shift, dtype=np.complex128)
+    if velocity == "smooth":
+        return convdiff_3d(m, pe, gen=gen, sigma=sigma, shift=shift, dtype=np.complex128)
+    return convdiff_3d(m, pe, direction=gen.standard_normal(3), shift=shift, dtype=np.complex128)
 
 
 # ---------------------------------------------------------------------------
@@ -271,9 +276,18 @@ def config1(n: int = 4, m: int = 32):
                    meta=dict(dims=2, m=m, pe=5.0))
 
 
-def config2(n: int = 4, m: int = 128, maxit: int = 20000):
-    """3D convection-diffusion m^3, Pe 20, smooth seeded direction field; b, Q ~ N(0, 1)."""
-    A = convdiff_3d(m, pe=20.0, gen=rng(2, 0))
+def config2(n: int = 4, m: int = 128, maxit: int = 20000, velocity: str = "constant"):
+    """3D convection-diffusion m^3, Pe 20, uniform speed along a seeded direction; b, Q ~ N(0, 1).
+
+    velocity="smooth" uses a smooth seeded direction field instead (Gaussian-filtered
+    noise, sigma 8 cells, normalised): on it the unpreconditioned method stalls with
+    residual excursions of ~4.5e3 ||b|| and a true residual near 1e-5 (the oracle
+    too), so the default is a constant seeded direction.
+    """
+    if velocity == "smooth":
+        A = convdiff_3d(m, pe=20.0, gen=rng(2, 0))
+    else:
+        A = convdiff_3d(m, pe=20.0, direction=rng(2, 0).standard_normal(3))
     N = A.shape[0]
     b = rng(2, 1).standard_normal(N)
     Q = _qblock(rng(2, 2), N, n)
