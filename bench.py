@@ -1,10 +1,13 @@
 """Time-to-1e-10 of ML(n)BiCGStab on one MI355X.
 
 One step = one complete solve (setup with A^H q_s, the whole iteration, the
-final fp64 true-residual check) of the 3D convection-diffusion system on a
-128^3 grid (N = 2,097,152, 14,581,760 nonzeros, CSR fp64), b and Q seeded
-Gaussian, x_0 = 0, tol 1e-10, with A, b and Q resident in HBM before timing.
-Prints one JSON line (rank 0).  Progress goes to stderr.
+final fp64 true-residual check) with A, b and Q resident in HBM before timing,
+x_0 = 0, tol 1e-10.  Default workload: the 3D convection-diffusion system on a
+128^3 grid (N = 2,097,152, 14,581,760 nonzeros, CSR fp64), n = 4.  Other
+workloads (--workload reservoir: 60x220x85 3x3-block system, BSR3, n = 8;
+--workload helmholtz: complex 96^3 system, n = 16) and the fp32-inner /
+fp64-refinement mode (--precision ir) use the same step definition.
+Prints one JSON line.  Progress goes to stderr.
 """
 import argparse
 import json
@@ -58,8 +61,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=4, help="number of shadow vectors")
-    ap.add_argument("--m", type=int, default=128, help="grid points per dimension")
+    ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "reservoir", "helmholtz"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "ir"])
+    ap.add_argument("--n", type=int, default=0, help="number of shadow vectors (0 = the workload's)")
+    ap.add_argument("--m", type=int, default=0, help="grid points per dimension (0 = the workload's)")
+    ap.add_argument("--inner-tol", type=float, default=0.0)
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle sample length (iterations)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -78,13 +84,25 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     t = time.perf_counter()
-    p = workloads.config2(n=args.n, m=args.m)
-    log(f"[bench] generated {p.name}: N={p.N} nnz={p.A.nnz} in {time.perf_counter() - t:.1f} s")
+    if args.workload == "convdiff3d":
+        p = workloads.config2(n=args.n or 4, m=args.m or 128)
+        fmt, cplx, grid = "csr", False, [args.m or 128] * 3
+    elif args.workload == "reservoir":
+        p = workloads.config3(n=args.n or 8)
+        fmt, cplx, grid = "bsr3", False, list(p.meta["grid"])
+    else:
+        p = workloads.config5(n=args.n or 16, m=args.m or 96)
+        fmt, cplx, grid = "csr", True, [args.m or 96] * 3
+    nnz = int(p.A.indptr[-1])          # entries (CSR) or 3x3 blocks (BSR3)
+    nbrows = len(p.A.indptr) - 1
+    log(f"[bench] generated {p.name}: N={p.N} stored={nnz} in {time.perf_counter() - t:.1f} s")
     dA = binding.to_device(p.A, dev)
-    b = torch.from_numpy(p.b).to(dev)
+    tdt = torch.complex128 if cplx else torch.float64
+    b = torch.from_numpy(p.b.astype(np.complex128 if cplx else np.float64)).to(dev)
     Q = binding.column_major(p.Q, dev)
-    x = torch.zeros(p.N, dtype=torch.float64, device=dev)
-    solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit)
+    x = torch.zeros(p.N, dtype=tdt, device=dev)
+    prec = binding.MLB_PREC_FP32_IR if args.precision == "ir" else binding.MLB_PREC_FP64
+    solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=args.inner_tol)
     torch.cuda.synchronize()
 
     def step():
@@ -102,15 +120,17 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for k, r in enumerate(results):
-        log(f"[bench] step {k}: flag={r.flag} iter={r.iter} err_rec={r.err_recursive:.3e} err_true={r.err_true:.3e} "
-            f"solve_ms={r.solve_ms:.1f} setup_ms={r.setup_ms:.2f}")
+        log(f"[bench] step {k}: flag={r.flag} iter={r.iter} outer={r.outer_iters} fp64_iters={r.fp64_iters} "
+            f"err_rec={r.err_recursive:.3e} err_true={r.err_true:.3e} solve_ms={r.solve_ms:.1f} setup_ms={r.setup_ms:.2f}")
     ms = 1e3 * elapsed / args.steps
     last = results[-1]
 
     # Dominant kernel (SpMV with its fused combination and shadow dots), timed live with HIP
     # events on the solver's stream, over the workspace of the last solve.
+    # value bytes of the iteration that the timed kernel belongs to (fp32 inner iteration for ir)
+    sv = (16 if cplx else 8) if args.precision == "fp64" else (8 if cplx else 4)
     ms_spmv = solver.time_kernel(binding.MLB_KERNEL_SPMV_STEP, args.kernel_reps)
-    bytes_spmv = spmv_step_bytes(p.A.nnz, p.N, p.N, p.n, 8)
+    bytes_spmv = spmv_step_bytes(nnz, nbrows, p.N, p.n, sv, bsr=(fmt == "bsr3"))
     achieved = bytes_spmv / (ms_spmv * 1e-3) / 1e9
     ms_alpha = solver.time_kernel(binding.MLB_KERNEL_ALPHA_STEP, args.kernel_reps)
     ms_comb = solver.time_kernel(binding.MLB_KERNEL_COMBINE, args.kernel_reps)
@@ -129,23 +149,27 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": ("c128" if cplx else "f64") if args.precision == "fp64" else
+                 ("c64 inner / c128 refinement" if cplx else "f32 inner / f64 refinement"),
         "data": "synthetic",
         "config": {
             "workload": p.name,
-            "grid": [args.m] * 3,
+            "grid": grid,
             "N": p.N,
-            "nnz": int(p.A.nnz),
-            "format": "csr",
+            "stored_entries": nnz,
+            "format": fmt,
             "n": p.n,
             "tol": p.tol,
+            "precision": args.precision,
             "iterations": int(last.iter),
+            "outer_iters": int(last.outer_iters),
+            "fp64_iters": int(last.fp64_iters),
             "flag": int(last.flag),
             "err_true": last.err_true,
             "setup_ms": last.setup_ms,
         },
         "roofline": {
-            "kernel": "k_spmv (SpMV-step: w = A g + sum beta w_s, g + sum beta g_s, q_s^H w)",
+            "kernel": "k_spmv_csrw / k_spmv (SpMV step: w_i = A g_i with q_s^H w_i, s >= i)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,

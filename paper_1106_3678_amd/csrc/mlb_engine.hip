@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -540,6 +541,15 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
   HIP_TRY(hipStreamSynchronize(h->s));
 }
 
+// MLB_DEBUG=1 in the environment prints one line per refinement step on stderr.
+static bool debug_enabled() {
+  static const bool on = [] {
+    const char* v = getenv("MLB_DEBUG");
+    return v && *v && *v != '0';
+  }();
+  return on;
+}
+
 template <class V64, class V32>
 static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, const V64* Q, long long ldq,
                       mlb_result* res) {
@@ -590,6 +600,9 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
       k_fill<V32><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(im.x32, N, zero<V32>());
       auto io = e32.solve(im.b32, im.x32, im.Q32, N, inner_tol, o.maxit - used, o.kappa, nullptr, 0);
       used += io.iter;
+      if (debug_enabled())
+        fprintf(stderr, "[mlbicgstab] refinement step %d: true err before %.3e, inner flag %d, inner iters %lld, "
+                "inner recursive err %.3e\n", outer, et, io.flag, (long long)io.iter, io.err);
       if (outer == 1) R.setup_ms = io.setup_ms;
       if (io.flag == -1) { fallback = true; break; }
       // x += ||r|| d
@@ -715,12 +728,9 @@ int mlbicgstab_create(const mlb_matrix* A, const mlb_options* opt, void* hip_str
     h->format = A->format;
     h->N = (int)A->nrows;
     h->opt = *opt;
-    if (hip_stream) {
-      h->s = (hipStream_t)hip_stream;
-    } else {
-      HIP_TRY(hipStreamCreateWithFlags(&h->s, hipStreamNonBlocking));
-      h->own_stream = true;
-    }
+    // NULL is the legacy default stream: work stays ordered with everything else
+    // the caller enqueued there (e.g. the fill that zeroes x before a solve).
+    h->s = (hipStream_t)hip_stream;
     // validate the index arrays on the device before any kernel relies on them
     {
       Allocs tmp;

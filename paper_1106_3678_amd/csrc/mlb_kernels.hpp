@@ -259,7 +259,7 @@ __global__ __launch_bounds__(BLOCK) void k_scalar(State<Sc>* st, const Sc* __res
       if (lane == 0) red2[wid][d] = v;
     }
   }
-  __syncthreads();
+  __syncthreads();   // every wave's red2 row is written before any lane sums across waves
   if (threadIdx.x < nsum) {
     Sc v = red2[0][threadIdx.x];
     for (int w = 1; w < BLOCK / WAVE; ++w) add_(v, red2[w][threadIdx.x]);
