@@ -40,6 +40,26 @@ def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False):
     return mat + vec_avg * N * sv
 
 
+def measured_traffic(workload):
+    """HBM bytes per SpMV-step launch from the committed rocprofv3 counter summary, or None when
+    the kernel source has changed since the counters were taken (or no summary exists)."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"spmv_step_{workload}.md")
+    src = os.path.join(ROOT, "paper_1106_3678_amd", "csrc", "mlb_kernels.hpp")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    m_h = re.search(r"^kernel_source_sha256: ([0-9a-f]+)", text, re.M)
+    if not m_t or not m_h:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_h.group(1):
+        return None
+    return int(m_t.group(1))
+
+
 def cpu_baseline(p, iters_gpu, sample_iters):
     """The oracle on this host: time a bounded sample of the same solve, scale to the full iteration count."""
     from threadpoolctl import threadpool_limits
@@ -66,9 +86,13 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="number of shadow vectors (0 = the workload's)")
     ap.add_argument("--m", type=int, default=0, help="grid points per dimension (0 = the workload's)")
     ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi"],
+                    help="auto: block Jacobi for the reservoir workload, none otherwise")
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle sample length (iterations)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--calib-copy", type=float, default=0.0,
+                    help="also run a plain device copy of this many GiB 3 times (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -94,6 +118,10 @@ def main():
         p = workloads.config5(n=args.n or 16, m=args.m or 96)
         fmt, cplx, grid = "csr", True, [args.m or 96] * 3
     nnz = int(p.A.indptr[-1])          # entries (CSR) or 3x3 blocks (BSR3)
+    profile_key = {"convdiff3d": f"convdiff3d_m{args.m or 128}_n{p.n}", "reservoir": f"reservoir_n{p.n}",
+                   "helmholtz": f"helmholtz_m{args.m or 96}_n{p.n}"}[args.workload]
+    if args.precision != "fp64":
+        profile_key += "_ir"
     nbrows = len(p.A.indptr) - 1
     log(f"[bench] generated {p.name}: N={p.N} stored={nnz} in {time.perf_counter() - t:.1f} s")
     dA = binding.to_device(p.A, dev)
@@ -102,7 +130,9 @@ def main():
     Q = binding.column_major(p.Q, dev)
     x = torch.zeros(p.N, dtype=tdt, device=dev)
     prec = binding.MLB_PREC_FP32_IR if args.precision == "ir" else binding.MLB_PREC_FP64
-    solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=args.inner_tol)
+    use_jacobi = args.precond == "jacobi" or (args.precond == "auto" and args.workload == "reservoir")
+    solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=args.inner_tol,
+                            precond=binding.MLB_PRECOND_JACOBI if use_jacobi else binding.MLB_PRECOND_NONE)
     torch.cuda.synchronize()
 
     def step():
@@ -137,6 +167,16 @@ def main():
     log(f"[bench] spmv-step {ms_spmv * 1e3:.1f} us/launch -> {achieved:.0f} GB/s ; alpha {ms_alpha * 1e3:.1f} us ; "
         f"combine {ms_comb * 1e3:.1f} us")
     solver.close()
+    if args.calib_copy > 0:
+        # a plain copy kernel of known size: reads and writes calib-copy GiB per launch
+        nel = int(args.calib_copy * (1 << 30) / 8)
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nel * 8} bytes read and written per launch, 3 launches")
+        del src, dst
 
     line = {
         "metric": "time-to-1e-10 residual",
@@ -161,6 +201,7 @@ def main():
             "n": p.n,
             "tol": p.tol,
             "precision": args.precision,
+            "preconditioner": "block Jacobi (right)" if use_jacobi else "none",
             "iterations": int(last.iter),
             "outer_iters": int(last.outer_iters),
             "fp64_iters": int(last.fp64_iters),
@@ -175,7 +216,7 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(profile_key),
             "bytes_per_launch": bytes_spmv,
             "us_per_launch": ms_spmv * 1e3,
         },

@@ -47,6 +47,7 @@ enum {
 enum { MLB_R64 = 0, MLB_C128 = 1 };          /* value type of A, b, x, Q        */
 enum { MLB_CSR = 0, MLB_BSR3 = 1 };          /* storage of A                     */
 enum { MLB_PREC_FP64 = 0, MLB_PREC_FP32_IR = 1 };
+enum { MLB_PRECOND_NONE = 0, MLB_PRECOND_JACOBI = 1 };
 
 #define MLB_MAX_N 32                          /* largest number of shadow vectors */
 
@@ -80,13 +81,24 @@ typedef struct {
  * an fp64 iterative-refinement loop (r = b - A x, x += d in fp64) that stops
  * on the TRUE residual ||b - A x|| / ||b|| < tol.  This mode is an addition of
  * this library; the paper does not discuss precision.  inner_tol (default
- * 1e-5 when <= 0) is the relative tolerance of each inner solve and
+ * 1e-6 when <= 0) is the relative tolerance of each inner solve (raised to
+ * 0.25 tol / ||r|| / ||b|| when that is larger, so the last step is not
+ * over-solved; an inner solve whose residual has not halved for
+ * max(300, 20 n) iterations also ends) and
  * max_outer (default 30 when <= 0) bounds the refinement steps; if a
  * refinement step gains less than 10x, or an inner solve breaks down, the
  * remaining work is done by the fp64 iteration.
  *
  * record_iterates = K > 0 stores x_1 .. x_K (K <= maxit) in the device array
  * iterates (N x K, column-major, ld = N, same dtype as x) during an fp64 solve.
+ *
+ * precond = MLB_PRECOND_JACOBI runs Algorithm 7.1 (Section 7) with M = the
+ * block diagonal of A (its 3x3 diagonal blocks for BSR3, its diagonal for CSR),
+ * applied from the right: the iteration runs on A M^{-1} y = b from
+ * y_0 = M x_0 and returns x = M^{-1} y.  The residual, the stopping test and
+ * f_s = M^{-H} A^H q_s are those of Algorithm 7.1.  create() fails with
+ * MLB_EINVAL if a (block) row has no stored diagonal entry or a singular one.
+ * MLB_PRECOND_NONE (0) is M = I, Algorithm 4.1.
  */
 typedef struct {
   int32_t n;
@@ -98,6 +110,7 @@ typedef struct {
   int32_t max_outer;
   int32_t record_iterates;
   void* iterates;           /* device, N x record_iterates, or NULL            */
+  int32_t precond;          /* MLB_PRECOND_NONE or MLB_PRECOND_JACOBI          */
 } mlb_options;
 
 typedef struct {
@@ -140,12 +153,14 @@ int mlbicgstab_destroy(mlb_handle h);
 const char* mlbicgstab_last_error(void);
 
 /*
- * Kernel timing for roofline figures: launches the solver's SpMV kernel
- * (w = A g with its fused combination and shadow dot products, as one inner
- * step of the fp64 iteration launches it) `reps` times on the solver's stream
- * over the workspace left by the last solve, bracketed by HIP events, and
- * stores the mean duration in *ms_per_launch.  Requires a prior solve().
- * The workspace contents are scrambled afterwards.
+ * Kernel timing for roofline figures: replays `reps` cycles of the fp64 (or,
+ * for MLB_PREC_FP32_IR, the fp32) iteration on the solver's stream over the
+ * workspace left by the last solve -- the same kernels in the same order as in
+ * a solve, with the one-workgroup coefficient recurrences left out -- and
+ * brackets every launch of the requested kernel class with a pair of HIP
+ * events.  *ms_per_launch receives the mean bracketed duration.  Requires a
+ * prior solve() whose Q is still allocated (it is read again); scrambles the
+ * library's workspace (not b, x or Q).
  */
 int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* ms_per_launch);
 

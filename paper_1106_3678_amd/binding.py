@@ -18,6 +18,7 @@ MLB_EINVAL, MLB_ENOMEM, MLB_EHIP, MLB_EUNSUPPORTED = -2, -3, -4, -5
 MLB_R64, MLB_C128 = 0, 1
 MLB_CSR, MLB_BSR3 = 0, 1
 MLB_PREC_FP64, MLB_PREC_FP32_IR = 0, 1
+MLB_PRECOND_NONE, MLB_PRECOND_JACOBI = 0, 1
 MLB_MAX_N = 32
 MLB_KERNEL_SPMV_STEP, MLB_KERNEL_ALPHA_STEP, MLB_KERNEL_COMBINE = 0, 1, 2
 
@@ -45,6 +46,7 @@ class mlb_options(ctypes.Structure):
         ("max_outer", ctypes.c_int32),
         ("record_iterates", ctypes.c_int32),
         ("iterates", ctypes.c_void_p),
+        ("precond", ctypes.c_int32),
     ]
 
 
@@ -194,14 +196,14 @@ class Solver:
 
     def __init__(self, dmat: DeviceMatrix, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
                  precision: int = MLB_PREC_FP64, inner_tol: float = 0.0, max_outer: int = 0,
-                 record_iterates: int = 0, iterates=None, stream=None):
+                 record_iterates: int = 0, iterates=None, stream=None, precond: int = MLB_PRECOND_NONE):
         import torch
 
         self.dmat = dmat
         self.n = n
         self.iterates = iterates
         self.opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, max_outer, record_iterates,
-                               iterates.data_ptr() if iterates is not None else None)
+                               iterates.data_ptr() if iterates is not None else None, precond)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.h = mlbicgstab_create(dmat.descriptor(), self.opt, self.stream.cuda_stream)
 

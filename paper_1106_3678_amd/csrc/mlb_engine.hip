@@ -22,6 +22,7 @@
 
 #include "../../include/mlbicgstab.h"
 #include "mlb_kernels.hpp"
+#include "mlb_precond.hpp"
 #include "mlb_transpose.hpp"
 
 namespace mlb {
@@ -64,7 +65,18 @@ static int grid_for(long long work, int cap) {
   return (int)std::min<long long>(g, cap);
 }
 
-constexpr int MAX_GRID = 2048;      // workgroups of a streaming pass (8 per CU)
+// Upper bound on the workgroups of a streaming pass (8 per CU on a 256-CU
+// MI355X).  MLB_MAX_GRID in the environment lowers or raises it (a tuning knob;
+// read once).
+static int max_grid() {
+  static const int g = [] {
+    const char* v = getenv("MLB_MAX_GRID");
+    const int x = v ? atoi(v) : 0;
+    return x >= 64 && x <= 65536 ? x : 2048;
+  }();
+  return g;
+}
+#define MAX_GRID max_grid()
 
 // ------------------------------------------------------------------ matrices
 
@@ -143,19 +155,38 @@ static Mat<V> build_transpose(const Mat<V>& A, Allocs& al, hipStream_t s) {
 
 static int bucket(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
+// Launches the SpMV kernel for A's format and lanes-per-row with epilogue MODE.
+// With grid == 0 nothing is launched and the kernel's occupancy (workgroups per
+// CU) is returned instead.
+template <class K>
+static int occupancy_of(K kernel) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    per_cu = 4;
+  }
+  return std::max(per_cu, 1);
+}
+
 template <class V, class Sc, int MODE, int ND>
-static void launch_spmv_nd(const Mat<V>& A, int grid, hipStream_t s, State<Sc>* st, Sc* part, const SpmvArgs<V>& a,
-                           int phase, int i, int j, int n, int flags) {
+static int launch_spmv_nd(const Mat<V>& A, int grid, hipStream_t s, State<Sc>* st, Sc* part, const SpmvArgs<V>& a,
+                          int phase, int i, int j, int n, int flags) {
 #define MLB_SPMV_CASE(L)                                                                                     \
-  if (A.format == MLB_CSR)                                                                                   \
+  if (A.format == MLB_CSR) {                                                                                 \
+    if (!grid) return occupancy_of(k_spmv<V, Sc, ND, L, 0, MODE>);                                          \
     k_spmv<V, Sc, ND, L, 0, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);                \
-  else                                                                                                       \
-    k_spmv<V, Sc, ND, L, 1, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);
+  } else {                                                                                                   \
+    if (!grid) return occupancy_of(k_spmv<V, Sc, ND, L, 1, MODE>);                                          \
+    k_spmv<V, Sc, ND, L, 1, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);                \
+  }
 #define MLB_SPMV_WCASE(L)                                                                                    \
-  if (A.format == MLB_CSR)                                                                                   \
+  if (A.format == MLB_CSR) {                                                                                 \
+    if (!grid) return occupancy_of(k_spmv_csrw<V, Sc, ND, L, MODE>);                                        \
     k_spmv_csrw<V, Sc, ND, L, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, flags);                             \
-  else                                                                                                       \
-    k_spmv<V, Sc, ND, L, 1, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);
+  } else {                                                                                                   \
+    if (!grid) return occupancy_of(k_spmv<V, Sc, ND, L, 1, MODE>);                                          \
+    k_spmv<V, Sc, ND, L, 1, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);                \
+  }
   switch (A.lpr) {
     case 4: MLB_SPMV_WCASE(4) break;
     case 8: MLB_SPMV_WCASE(8) break;
@@ -164,11 +195,23 @@ static void launch_spmv_nd(const Mat<V>& A, int grid, hipStream_t s, State<Sc>* 
   }
 #undef MLB_SPMV_CASE
 #undef MLB_SPMV_WCASE
+  return 0;
+}
+
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess || cus <= 0) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  return cus;
 }
 
 // Resets the device scalars before a solve.
 template <class Sc>
-__global__ void k_init_state(State<Sc>* st, double tol, long long maxit, double kappa, int* host_done) {
+__global__ void k_init_state(State<Sc>* st, double tol, long long maxit, double kappa, int* host_done,
+                             long long stag_window) {
   st->done = 0;
   st->flag = 1;
   st->iter = 0;
@@ -184,6 +227,9 @@ __global__ void k_init_state(State<Sc>* st, double tol, long long maxit, double 
   for (int q = 0; q < NMAX * NMAX; ++q) st->S[q] = zero<Sc>();
   for (int q = 0; q < 8; ++q) st->aux[q] = zero<Sc>();
   st->host_done = host_done;
+  st->best_err = 0.0;
+  st->best_k = 0;
+  st->stag_window = stag_window;
 }
 
 
@@ -221,8 +267,20 @@ struct Engine {
     gt = al.get<V>(N);
     z = al.get<V>(N);
     st = al.get<State<Sc>>(1);
-    grid_vec = grid_for(N, MAX_GRID);
-    grid_spmv = grid_for(A.nbrows, MAX_GRID);
+    // One resident round of workgroups: CUs x the SpMV-step kernel's occupancy for
+    // the SpMV passes (no partly filled second round), 8 per CU for the streaming
+    // vector passes; MLB_MAX_GRID caps both.
+    const int cus = device_cus();
+    SpmvArgs<V> probe{};
+    int occ = 4;
+    switch (nb) {
+      case 4: occ = launch_spmv_nd<V, Sc, SM_STEP, 4>(A, 0, s, st, nullptr, probe, 0, 0, 0, n, 0); break;
+      case 8: occ = launch_spmv_nd<V, Sc, SM_STEP, 8>(A, 0, s, st, nullptr, probe, 0, 0, 0, n, 0); break;
+      case 16: occ = launch_spmv_nd<V, Sc, SM_STEP, 16>(A, 0, s, st, nullptr, probe, 0, 0, 0, n, 0); break;
+      default: occ = launch_spmv_nd<V, Sc, SM_STEP, 32>(A, 0, s, st, nullptr, probe, 0, 0, 0, n, 0); break;
+    }
+    grid_vec = grid_for(N, std::min(MAX_GRID, 8 * cus));
+    grid_spmv = grid_for(A.nbrows, std::min(MAX_GRID, occ * cus));
     part = al.get<Sc>((size_t)std::max(grid_vec, grid_spmv) * (NMAX + 1));
     HIP_TRY(hipHostMalloc((void**)&host_done, sizeof(int), hipHostMallocMapped));
     *host_done = 0;
@@ -243,8 +301,32 @@ struct Engine {
 
   // ---- single launches --------------------------------------------------
 
+  bool launch_scalars = true;   // false while timing kernels (same kernel work, no recurrence)
+  int force_flags = 0;          // OR-ed into every pass's flags (timing: F_IGNORE_DONE)
+  // Timing hook: HIP event pairs recorded around every launch of one kernel class.
+  int ev_kernel = -1;
+  std::vector<hipEvent_t>* ev_list = nullptr;
+  struct Bracket {
+    Engine& e;
+    bool on;
+    Bracket(Engine& e_, int kind) : e(e_), on(e_.ev_kernel == kind && e_.ev_list) {
+      if (on) record();
+    }
+    ~Bracket() {
+      if (on) record();
+    }
+    void record() {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) == hipSuccess) {
+        (void)hipEventRecord(ev, e.s);
+        e.ev_list->push_back(ev);
+      }
+    }
+  };
+
   // Sum the partials of the pass just launched and run the recurrence of `phase`.
   void scalar(int nblocks, int stride, int nsum, int phase, int i, int j) {
+    if (!launch_scalars) return;
     switch (stride) {
       case 4: k_scalar<Sc, 4><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
       case 5: k_scalar<Sc, 5><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
@@ -274,11 +356,12 @@ struct Engine {
     SpmvArgs<V> a{};
     a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
     a.xin = u; a.out1 = zout;
-    launch_spmv_nd<V, Sc, SM_OMEGA, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_OMEGA, 0, 0, n, 0);
+    launch_spmv_nd<V, Sc, SM_OMEGA, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_OMEGA, 0, 0, n, force_flags);
     scalar(grid_spmv, 4, 2, PH_SPMV_OMEGA, 0, 0);
   }
   // G_i = g + sum_{s<i} beta_s G_s (beta from the last PH_COMBINE)
   void gcomb(const V* gin, int i, int flags = 0) {
+    flags |= force_flags;
     k_gcomb<V, Sc><<<grid_vec, BLOCK, 0, s>>>(st, N, gin, G, N, i, G + (size_t)i * N, flags);
   }
   // w_i = A G_i ; S[s][i] = q_s^H w_i, s = i..n-1.  With gin != G_i the input is
@@ -289,6 +372,8 @@ struct Engine {
     V* Gi = G + (size_t)i * N;
     a.xin = gin; a.out1 = W + (size_t)i * N; a.out2 = gin == Gi ? nullptr : Gi;
     a.Q = Q; a.ldq = ldq; a.d0 = i; a.nd = n - i;
+    flags |= force_flags;
+    Bracket br(*this, MLB_KERNEL_SPMV_STEP);
     switch (nb) {
       case 4: launch_spmv_nd<V, Sc, SM_STEP, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
       case 8: launch_spmv_nd<V, Sc, SM_STEP, 8>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
@@ -300,6 +385,8 @@ struct Engine {
   void alpha(V* x, int i_prev, int d0, int nd, int phase, int i, int j, V* xrec, long long K, int flags = 0) {
     const V* gh = G + (size_t)i_prev * N;
     const V* w = W + (size_t)i_prev * N;
+    flags |= force_flags;
+    Bracket br(*this, MLB_KERNEL_ALPHA_STEP);
 #define MLB_ALPHA(B) \
   k_alpha<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, gh, r, w, Q, ldq, d0, nd, xrec, K, phase, i, j, n, flags)
     switch (nb) {
@@ -312,6 +399,8 @@ struct Engine {
     if (!(flags & F_SKIP_SCALAR)) scalar(grid_vec, nb + 1, nd + 1, phase, i, j);
   }
   void combine(int t0, int t1, int nf, int i, int j, int flags = 0) {
+    flags |= force_flags;
+    Bracket br(*this, MLB_KERNEL_COMBINE);
 #define MLB_COMB(B)                                                                                            \
   k_combine<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, r, W, G, N, t0, t1, gt, F, N, nf, PH_COMBINE, i, j, n, \
                                                  flags)
@@ -325,7 +414,8 @@ struct Engine {
     if (!(flags & F_SKIP_SCALAR) && nf > 0) scalar(grid_vec, nb, nf, PH_COMBINE, i, j);
   }
   void omega_update(V* x, V* xrec, long long K) {
-#define MLB_OM(B) k_omega<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, r, z, Q, ldq, n, xrec, K, PH_OMEGA_UPD, n, 0)
+#define MLB_OM(B) \
+  k_omega<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, r, z, Q, ldq, n, xrec, K, PH_OMEGA_UPD, n, force_flags)
     switch (nb) {
       case 4: MLB_OM(4); break;
       case 8: MLB_OM(8); break;
@@ -367,7 +457,7 @@ struct Engine {
 
   // Algorithm 7.1 with M = I from x (in: x_0, out: solution).
   Out solve(const V* b, V* x, const V* Q_, long long ldq_, double tol, long long maxit, double kappa, V* xrec,
-            long long K) {
+            long long K, long long stag_window = 0) {
     Q = Q_;
     ldq = ldq_;
     *(volatile int*)host_done = 0;
@@ -375,7 +465,7 @@ struct Engine {
     HIP_TRY(hipEventCreate(&t0));
     HIP_TRY(hipEventCreate(&t1));
     HIP_TRY(hipEventRecord(t0, s));
-    k_init_state<Sc><<<1, 1, 0, s>>>(st, tol, maxit, kappa, host_done_dev);
+    k_init_state<Sc><<<1, 1, 0, s>>>(st, tol, maxit, kappa, host_done_dev, stag_window);
     // r_0 = b - A x_0, ||b||, e_0 = q_1^H r_0, early exit
     spmv_resid(A, x, b, r, Q, PH_SETUP);
     // f_s = A^H q_s, s = 1..n-1
@@ -407,10 +497,10 @@ struct Engine {
     return o;
   }
 
-  // ||b - A x|| and ||b|| in this engine's precision (sums left in st->aux).
-  void resid_sums(const V* b, const V* x, V* out) {
-    k_init_state<Sc><<<1, 1, 0, s>>>(st, 1.0, 1, 0.0, nullptr);
-    spmv_resid(A, x, b, out, nullptr, PH_NONE);
+  // ||b - M x|| and ||b|| in this engine's precision (sums left in st->aux).
+  void resid_sums(const Mat<V>& M, const V* b, const V* x, V* out) {
+    k_init_state<Sc><<<1, 1, 0, s>>>(st, 1.0, 1, 0.0, nullptr, 0);
+    spmv_resid(M, x, b, out, nullptr, PH_NONE);
   }
   void read_aux(double* rr, double* bb) {
     State<Sc> h;
@@ -432,6 +522,10 @@ struct Impl {
   V32* x32 = nullptr;   // inner solution
   V32* Q32 = nullptr;   // fp32 shadow block (ld = N)
   V64* r64 = nullptr;   // fp64 residual b - A x
+  Mat<V64> A0;          // the caller's A (true residuals); the engines iterate on A M^{-1}
+  int bs = 1;           // 1 (CSR) or 3 (BSR3): size of the diagonal blocks of M
+  V64* Mblk = nullptr;  // diagonal (blocks) of A, when preconditioned
+  V64* Minv = nullptr;  // their inverses
   void release() {
     e64.release();
     if (has32) e32.release();
@@ -470,6 +564,8 @@ static void check_options(const mlb_options* opt) {
   if (!(opt->kappa >= 0.0) || !std::isfinite(opt->kappa)) throw Error{MLB_EINVAL, "kappa must be finite and >= 0"};
   if (opt->precision != MLB_PREC_FP64 && opt->precision != MLB_PREC_FP32_IR)
     throw Error{MLB_EINVAL, "precision must be MLB_PREC_FP64 or MLB_PREC_FP32_IR"};
+  if (opt->precond != MLB_PRECOND_NONE && opt->precond != MLB_PRECOND_JACOBI)
+    throw Error{MLB_EINVAL, "precond must be MLB_PRECOND_NONE or MLB_PRECOND_JACOBI"};
   if (opt->record_iterates < 0) throw Error{MLB_EINVAL, "record_iterates must be >= 0"};
   if (opt->record_iterates > 0) {
     if (!opt->iterates) throw Error{MLB_EINVAL, "record_iterates > 0 needs an iterates buffer"};
@@ -506,6 +602,33 @@ static Mat<V> user_matrix(const mlb_matrix* A) {
 template <class V64, class V32>
 static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& im) {
   Mat<V64> A = user_matrix<V64>(Adesc);
+  im.A0 = A;
+  im.bs = A.format == MLB_BSR3 ? 3 : 1;
+  if (h->opt.precond == MLB_PRECOND_JACOBI) {
+    // M = block diagonal of A; iterate on A M^{-1} (formed once)
+    const int b2 = im.bs * im.bs;
+    im.Mblk = h->al.get<V64>((size_t)A.nbrows * b2);
+    im.Minv = h->al.get<V64>((size_t)A.nbrows * b2);
+    V64* scaled = h->al.get<V64>((size_t)A.nnz * b2);
+    Allocs tmp;
+    int* bad = tmp.get<int>(1);
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), h->s));
+    const int g = grid_for(A.nbrows, 4096);
+    if (im.bs == 1) {
+      k_diag_inverse<V64, 1><<<g, BLOCK, 0, h->s>>>(A.rp, A.ci, A.val, A.nbrows, im.Mblk, im.Minv, bad);
+      k_right_scale<V64, 1><<<g, BLOCK, 0, h->s>>>(A.rp, A.ci, A.val, A.nbrows, im.Minv, scaled);
+    } else {
+      k_diag_inverse<V64, 3><<<g, BLOCK, 0, h->s>>>(A.rp, A.ci, A.val, A.nbrows, im.Mblk, im.Minv, bad);
+      k_right_scale<V64, 3><<<g, BLOCK, 0, h->s>>>(A.rp, A.ci, A.val, A.nbrows, im.Minv, scaled);
+    }
+    HIP_TRY(hipGetLastError());
+    int hb = 0;
+    HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipStreamSynchronize(h->s));
+    if (hb & 1) throw Error{MLB_EINVAL, "Jacobi preconditioner: a (block) row has no stored diagonal entry"};
+    if (hb & 2) throw Error{MLB_EINVAL, "Jacobi preconditioner: a diagonal (block) is singular"};
+    A.val = scaled;
+  }
   Mat<V64> AH = build_transpose(A, h->al, h->s);
   im.e64.init(A, AH, h->opt.n, h->s, h->al);
   im.r64 = h->al.get<V64>(h->N);
@@ -550,6 +673,31 @@ static bool debug_enabled() {
   return on;
 }
 
+// x <- M x (forward) or x <- M^{-1} x (back) for `cols` columns; no-op without a preconditioner.
+template <class V64, class V32>
+static void precond_map(mlb_solver* h, Impl<V64, V32>& im, V64* x, int cols, long long ld, bool back) {
+  if (!im.Minv || cols <= 0) return;
+  const V64* blk = back ? im.Minv : im.Mblk;
+  const int nbr = im.A0.nbrows;
+  const int g = grid_for((long long)nbr * cols, 4096);
+  if (im.bs == 1) k_block_apply<V64, 1><<<g, BLOCK, 0, h->s>>>(blk, x, nbr, cols, ld);
+  else k_block_apply<V64, 3><<<g, BLOCK, 0, h->s>>>(blk, x, nbr, cols, ld);
+}
+
+// The fp64 iteration (Algorithm 7.1) from the current x; with a preconditioner it
+// runs on A M^{-1} y = b with y_0 = M x and maps back x = M^{-1} y (also the
+// recorded iterates).
+template <class V64, class V32>
+static typename Engine<V64>::Out fp64_iteration(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x,
+                                                const V64* Q, long long ldq, long long maxit, V64* xrec, long long K) {
+  const mlb_options& o = h->opt;
+  precond_map(h, im, x, 1, h->N, false);
+  auto out = im.e64.solve(b, x, Q, ldq, o.tol, maxit, o.kappa, xrec, K);
+  precond_map(h, im, x, 1, h->N, true);
+  if (xrec) precond_map(h, im, xrec, (int)std::min<long long>(K, std::max<long long>(out.iter, 0)), h->N, true);
+  return out;
+}
+
 template <class V64, class V32>
 static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, const V64* Q, long long ldq,
                       mlb_result* res) {
@@ -562,27 +710,28 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
   mlb_result R{};
   int flag = 1;
   if (o.precision == MLB_PREC_FP64) {
-    auto out = im.e64.solve(b, x, Q, ldq, o.tol, o.maxit, o.kappa, (V64*)o.iterates, o.record_iterates);
+    auto out = fp64_iteration(h, im, b, x, Q, ldq, o.maxit, (V64*)o.iterates, o.record_iterates);
     flag = out.flag;
     R.iter = out.iter;
     R.fp64_iters = out.iter;
     R.err_recursive = out.err;
     R.setup_ms = out.setup_ms;
   } else {
-    // fp32 inner iteration inside fp64 iterative refinement
+    // fp32 inner iteration inside fp64 iterative refinement (an addition of this library)
     auto& e32 = im.e32;
     for (int c = 0; c < o.n; ++c)
       k_cast<V32, V64, typename traits<V64>::wide><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(
           im.Q32 + (size_t)c * N, Q + (size_t)c * ldq, N, im.e64.st, 0);
-    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-6;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 30;
+    const long long window = std::max(300, 20 * o.n);   // stagnation window of the inner iteration
     long long used = 0;
     double prev = INFINITY;
     bool fallback = false;
     int outer = 0;
     flag = 1;
     while (true) {
-      im.e64.resid_sums(b, x, im.r64);
+      im.e64.resid_sums(im.A0, b, x, im.r64);
       double rr, bb;
       im.e64.read_aux(&rr, &bb);
       const double bn = bb > 0 ? std::sqrt(bb) : 1.0;
@@ -598,31 +747,39 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
       k_cast<V32, V64, typename traits<V64>::wide><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(im.b32, im.r64, N,
                                                                                           im.e64.st, 1);
       k_fill<V32><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(im.x32, N, zero<V32>());
-      auto io = e32.solve(im.b32, im.x32, im.Q32, N, inner_tol, o.maxit - used, o.kappa, nullptr, 0);
+      // the last refinement step only needs to bring ||r|| from et down to tol: do not over-solve it
+      const double step_tol = std::max(inner_tol, 0.25 * o.tol / et);
+      auto io = e32.solve(im.b32, im.x32, im.Q32, N, step_tol, o.maxit - used, o.kappa, nullptr, 0, window);
       used += io.iter;
+      if (outer == 1) R.setup_ms = io.setup_ms;
       if (debug_enabled())
         fprintf(stderr, "[mlbicgstab] refinement step %d: true err before %.3e, inner flag %d, inner iters %lld, "
                 "inner recursive err %.3e\n", outer, et, io.flag, (long long)io.iter, io.err);
-      if (outer == 1) R.setup_ms = io.setup_ms;
-      if (io.flag == -1) { fallback = true; break; }
-      // x += ||r|| d
-      k_axpy_wide<V64, V32, typename traits<V64>::wide><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(x, im.x32, N,
-                                                                                             im.e64.st);
+      // an inner solve that broke down, or stagnated without halving the residual, ends the refinement
+      if (io.flag == -1 || !(io.err < 0.5)) { fallback = true; break; }
+      // x += ||r|| M^{-1} d  (d solves the scaled system in fp32)
+      const V64* minv = im.Minv;
+      if (im.bs == 1 || !minv)
+        k_axpy_wide_minv<V64, V32, typename traits<V64>::wide, 1><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(
+            x, im.x32, minv, N, im.e64.st);
+      else
+        k_axpy_wide_minv<V64, V32, typename traits<V64>::wide, 3><<<grid_for(N / 3, 4096), BLOCK, 0, h->s>>>(
+            x, im.x32, minv, N / 3, im.e64.st);
       HIP_TRY(hipGetLastError());
     }
     R.outer_iters = outer;
     R.iter = used;
     if (fallback) {
       long long left = std::max<long long>(1, o.maxit - used);
-      auto out = im.e64.solve(b, x, Q, ldq, o.tol, left, o.kappa, nullptr, 0);
+      auto out = fp64_iteration(h, im, b, x, Q, ldq, left, (V64*)nullptr, 0);
       flag = out.flag;
       R.fp64_iters = out.iter;
       R.iter = used + out.iter;
       R.err_recursive = out.err;
     }
   }
-  // true residual ||b - A x|| / ||b|| in fp64
-  im.e64.resid_sums(b, x, im.r64);
+  // true residual ||b - A x|| / ||b|| in fp64 with the caller's A
+  im.e64.resid_sums(im.A0, b, x, im.r64);
   double rr, bb;
   im.e64.read_aux(&rr, &bb);
   R.err_true = std::sqrt(rr) / (bb > 0 ? std::sqrt(bb) : 1.0);
@@ -639,35 +796,43 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
   return flag;
 }
 
+// Mean duration of one kernel class as it runs inside the iteration: whole cycles
+// are replayed (same kernels, same predecessors, same cache context; the one-
+// workgroup recurrences are left out and the done flag is ignored) and only the
+// requested kernel's launches are bracketed by HIP event pairs.
 template <class V>
 static double time_kernel_impl(Engine<V>& e, int kernel, int reps) {
-  hipEvent_t t0, t1;
-  HIP_TRY(hipEventCreate(&t0));
-  HIP_TRY(hipEventCreate(&t1));
-  const int fl = F_IGNORE_DONE | F_SKIP_SCALAR;
-  long long launches = 0;
-  auto one_round = [&]() {
-    if (kernel == MLB_KERNEL_SPMV_STEP) {
-      for (int i = 0; i < e.n; ++i, ++launches) e.spmv_step(i == 0 ? e.gt : e.G + (size_t)i * e.N, i, fl);
-    } else if (kernel == MLB_KERNEL_ALPHA_STEP) {
-      for (int i = 1; i <= e.n; ++i, ++launches)
-        e.alpha(e.z, i - 1, i % e.n, i < e.n ? e.n - i : 0, PH_INNER, i, 1, nullptr, 0, fl);
-    } else {
-      for (int i = 0; i < e.n; ++i, ++launches) e.combine(i, e.n, i, i, 1, fl);
+  Allocs tmp;
+  V* xs = tmp.get<V>(e.N);   // scratch iterate (the caller's x is not touched)
+  HIP_TRY(hipMemsetAsync(xs, 0, sizeof(V) * e.N, e.s));
+  std::vector<hipEvent_t> evs;
+  struct Restore {
+    Engine<V>& e;
+    std::vector<hipEvent_t>& evs;
+    ~Restore() {
+      e.launch_scalars = true;
+      e.force_flags = 0;
+      e.ev_kernel = -1;
+      e.ev_list = nullptr;
+      for (auto ev : evs) (void)hipEventDestroy(ev);
     }
-  };
-  one_round();   // warm-up
-  launches = 0;
-  HIP_TRY(hipEventRecord(t0, e.s));
-  for (int r = 0; r < reps; ++r) one_round();
-  HIP_TRY(hipEventRecord(t1, e.s));
-  HIP_TRY(hipEventSynchronize(t1));
+  } restore{e, evs};
+  e.launch_scalars = false;
+  e.force_flags = F_IGNORE_DONE;
+  e.cycle(1, xs, nullptr, 0);   // warm-up, not recorded
+  e.ev_kernel = kernel;
+  e.ev_list = &evs;
+  for (int r = 0; r < reps; ++r) e.cycle(1, xs, nullptr, 0);
+  HIP_TRY(hipStreamSynchronize(e.s));
   HIP_TRY(hipGetLastError());
-  float ms = 0;
-  HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
-  return launches > 0 ? ms / launches : 0.0;
+  double total = 0;
+  const size_t pairs = evs.size() / 2;
+  for (size_t k = 0; k < pairs; ++k) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, evs[2 * k], evs[2 * k + 1]));
+    total += ms;
+  }
+  return pairs ? total / pairs : 0.0;
 }
 
 template <class F>
@@ -707,6 +872,8 @@ int mlbicgstab_workspace_size(const mlb_matrix* A, const mlb_options* opt, size_
     size_t t = (size_t)(nbr + 1) * 4 + (size_t)A->nnz * 4 + (size_t)A->nnz * bs * sv;   // A^H
     t += c ? Engine<cplx<double>>::bytes(N, opt->n, grid) : Engine<double>::bytes(N, opt->n, grid);
     t += (size_t)N * sv;                                                                   // r64
+    if (opt->precond == MLB_PRECOND_JACOBI)                                                // M, M^{-1}, A M^{-1}
+      t += (size_t)nbr * bs * 2 * sv + (size_t)A->nnz * bs * sv;
     if (opt->precision == MLB_PREC_FP32_IR) {
       t += (size_t)A->nnz * bs * sv;                                                       // fp32 A, A^H values
       t += c ? Engine<cplx<float>>::bytes(N, opt->n, grid) : Engine<float>::bytes(N, opt->n, grid);

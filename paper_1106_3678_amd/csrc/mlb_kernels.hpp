@@ -67,6 +67,9 @@ struct State {
   Sc tg[NMAX];          // -t / omega (of the g columns)
   Sc beta[NMAX];        // pending beta coefficients
   Sc aux[8];            // PH_NONE results
+  double best_err;      // smallest err seen so far (stagnation guard)
+  long long best_k;     // iteration at which best_err last halved
+  long long stag_window;  // > 0: stop with flag 2 after this many iterations without halving
   int* host_done;       // host-mapped copy of `done` (may be null)
 };
 
@@ -148,6 +151,19 @@ __device__ inline void beta_tilde(State<Sc>* st, const Sc* d, int i, int n) {
   }
 }
 
+// Stagnation guard of the fp32 inner iteration (an addition of this library):
+// flag 2 once the residual has not halved for stag_window iterations.
+template <class Sc>
+__device__ inline bool stagnated(State<Sc>* st, double err, long long k) {
+  if (st->stag_window <= 0) return false;
+  if (err < 0.5 * st->best_err) {
+    st->best_err = err;
+    st->best_k = k;
+    return false;
+  }
+  return k - st->best_k >= st->stag_window;
+}
+
 template <class Sc>
 __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, int j, int n) {
   switch (phase) {
@@ -160,6 +176,8 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       st->bnrm2 = bn;
       double err = sqrt(re(sums[0])) / bn;
       st->err = err;
+      st->best_err = err;
+      st->best_k = 0;
       st->iter = 0;
       st->e = sums[2];
       if (!finite(err)) finish(st, -1);
@@ -173,6 +191,7 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (!finite(err)) { finish(st, -1); break; }
       if (err < st->tol) { finish(st, 0); break; }
       if (k >= st->maxit) { finish(st, 1); break; }
+      if (stagnated(st, err, k)) { finish(st, 2); break; }
       st->e = sums[1];                       // e = q_{i+1}^H r
       if (j >= 1) beta_tilde(st, sums + 1, i, n);
       break;
@@ -224,6 +243,7 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (!finite(err)) { finish(st, -1); break; }
       if (err < st->tol) { finish(st, 0); break; }
       if (k >= st->maxit) { finish(st, 1); break; }
+      if (stagnated(st, err, k)) { finish(st, 2); break; }
       st->e = sums[1];                       // e = q_1^H r
       beta_tilde(st, sums + 1, 0, n);
       break;
@@ -649,6 +669,26 @@ __global__ void k_cast(To* __restrict__ out, const From* __restrict__ in, long l
   for (long long i = blockIdx.x * (long long)BLOCK + threadIdx.x; i < N; i += (long long)gridDim.x * BLOCK) {
     auto w = convert<typename traits<From>::wide>(in[i]);
     out[i] = convert<To>(s * w);
+  }
+}
+
+// x (wide) += sqrt(re(st->aux[0])) * Minv d (narrow), Minv block diagonal (BS = 1 or 3);
+// without Minv: x += sqrt(re(st->aux[0])) * d.
+template <class Vw, class Vn, class Sc, int BS>
+__global__ void k_axpy_wide_minv(Vw* __restrict__ x, const Vn* __restrict__ d, const Vw* __restrict__ Minv,
+                                 int nbrows, const State<Sc>* st) {
+  const Vw s = from_real<Vw>(sqrt(re(st->aux[0])));
+  for (int row = blockIdx.x * BLOCK + threadIdx.x; row < nbrows; row += gridDim.x * BLOCK) {
+    Vw dv[BS];
+    for (int k = 0; k < BS; ++k) dv[k] = convert<Vw>(d[(long long)BS * row + k]);
+    for (int r = 0; r < BS; ++r) {
+      Vw t = dv[r];
+      if (Minv) {
+        t = zero<Vw>();
+        for (int k = 0; k < BS; ++k) t = axpy(t, Minv[(size_t)BS * BS * row + BS * r + k], dv[k]);
+      }
+      x[(long long)BS * row + r] = axpy(x[(long long)BS * row + r], s, t);
+    }
   }
 }
 

@@ -11,7 +11,27 @@ def gpu_available():
     return torch.cuda.is_available()
 
 
-def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None):
+def block_jacobi(A):
+    """(apply M^{-1}, apply M^{-H}) for M = the block diagonal of A (3x3 blocks for BSR, else the diagonal),
+    built from A's entries with numpy."""
+    import scipy.sparse as sp
+
+    if sp.isspmatrix_bsr(A):
+        nb = A.shape[0] // 3
+        blocks = np.zeros((nb, 3, 3), dtype=A.dtype)
+        for r in range(nb):
+            for q in range(A.indptr[r], A.indptr[r + 1]):
+                if A.indices[q] == r:
+                    blocks[r] = A.data[q]
+        Minv = np.linalg.inv(blocks)
+        MinvH = np.conj(np.transpose(Minv, (0, 2, 1)))
+        return (lambda v: np.einsum("rij,rj->ri", Minv, v.reshape(nb, 3)).reshape(-1),
+                lambda v: np.einsum("rij,rj->ri", MinvH, v.reshape(nb, 3)).reshape(-1))
+    d = A.diagonal()
+    return (lambda v: v / d, lambda v: v / np.conj(d))
+
+
+def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None, precond=0):
     """Solve problem p on the GPU; returns (result, x, iterates or None)."""
     from paper_1106_3678_amd import binding
 
@@ -25,7 +45,7 @@ def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None):
     K = min(record, mi)
     it = torch.zeros((K, p.N), dtype=dt, device="cuda") if K else None
     s = binding.Solver(dA, p.n, tol=p.tol, maxit=mi, kappa=p.kappa if kappa is None else kappa,
-                       precision=precision, inner_tol=inner_tol, record_iterates=K, iterates=it)
+                       precision=precision, inner_tol=inner_tol, record_iterates=K, iterates=it, precond=precond)
     try:
         res = s.solve(b, x, Q)
         torch.cuda.synchronize()
@@ -36,9 +56,11 @@ def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None):
     return res, xs, its
 
 
-def run_oracle(p, record=0, maxit=None, kappa=None):
+def run_oracle(p, record=0, maxit=None, kappa=None, precond=0, summation="blas"):
+    pre = block_jacobi(p.A) if precond else None
     return oracle.mlbicgstabt(p.A, p.b, p.Q, x0=p.x0, tol=p.tol, maxit=p.maxit if maxit is None else maxit,
-                              kappa=p.kappa if kappa is None else kappa, record_x=record)
+                              kappa=p.kappa if kappa is None else kappa, record_x=record, precond=pre,
+                              summation=summation)
 
 
 def rel(a, b):
@@ -51,7 +73,7 @@ def iters_close(a, b):
     return abs(a - b) <= max(1, int(0.05 * max(a, b)))
 
 
-def oracle_spread(p, base, K=20):
+def oracle_spread(p, base, K=20, precond=0):
     """How far the oracle itself moves under rounding-level changes.
 
     Re-runs the oracle (a) with its inner products summed in other orders
@@ -66,7 +88,7 @@ def oracle_spread(p, base, K=20):
     variants = [("exact", p.b), ("reversed", p.b), ("blas", p.b * (1 + 1e-15 * g.standard_normal(p.N)))]
     for summation, b in variants:
         o2 = oracle.mlbicgstabt(p.A, b, p.Q, x0=p.x0, tol=p.tol, maxit=p.maxit, kappa=p.kappa, record_x=K,
-                                summation=summation)
+                                summation=summation, precond=block_jacobi(p.A) if precond else None)
         kk = min(K, o2.iter, base.iter)
         for k in range(kk):
             it_spread = max(it_spread, rel(o2.x_history[k], base.x_history[k]))

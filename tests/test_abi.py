@@ -47,7 +47,7 @@ def _desc(binding, **kw):
 
 def _opt(binding, **kw):
     o = dict(n=4, tol=1e-10, maxit=100, kappa=0.0, precision=0, inner_tol=0.0, max_outer=0, record_iterates=0,
-             iterates=None)
+             iterates=None, precond=0)
     o.update(kw)
     return binding.mlb_options(**o)
 
@@ -57,6 +57,7 @@ def _opt(binding, **kw):
     dict(m=dict(nnz=-1)), dict(m=dict(row_ptr=None)),
     dict(o=dict(n=0)), dict(o=dict(tol=0.0)), dict(o=dict(tol=float("nan"))), dict(o=dict(maxit=0)),
     dict(o=dict(kappa=-1.0)), dict(o=dict(precision=5)), dict(o=dict(record_iterates=3)),
+    dict(o=dict(precond=7)),
 ])
 def test_create_rejects_bad_arguments(binding, bad):
     A = _desc(binding, **bad.get("m", {}))

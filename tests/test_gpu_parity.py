@@ -17,14 +17,15 @@ if not gpu_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 
-def check_parity(p, K=20, x_tol=1e-6, sensitive=False):
+def check_parity(p, K=20, x_tol=1e-6, sensitive=False, precond=0):
     """Strict bars; with sensitive=True each bar is widened to what the oracle's own
-    rounding-level spread (tests.gpu_util.oracle_spread) allows."""
-    res, x, its = run_gpu(p, record=K)
-    o = run_oracle(p, record=K)
+    rounding-level spread (tests.gpu_util.oracle_spread) allows.  precond=1 compares
+    Algorithm 7.1 with M = the block diagonal of A on both sides."""
+    res, x, its = run_gpu(p, record=K, precond=precond)
+    o = run_oracle(p, record=K, precond=precond)
     it_tol, n_tol, res_tol = 1e-8, max(1, int(0.05 * o.iter)), p.tol + 1e-12
     if sensitive:
-        s_it, s_n, s_true, s_x = oracle_spread(p, o, K)
+        s_it, s_n, s_true, s_x = oracle_spread(p, o, K, precond=precond)
         it_tol = max(it_tol, 10 * s_it)
         n_tol = max(n_tol, 2 * s_n)
         res_tol = max(res_tol, 3 * s_true)
@@ -72,6 +73,19 @@ def test_bsr3_small(grid, n):
     in another order moves its iteration count by up to ~10% and, on the 9x14x7 grid, its x_20 by
     ~1e-6, so these cases use bars derived from the oracle's rounding-order spread."""
     check_parity(workloads.config3(n=n, grid=grid, maxit=8000), sensitive=True)
+
+
+@pytest.mark.parametrize("grid,n", [((8, 10, 6), 4), ((12, 16, 6), 8), ((9, 14, 7), 4)])
+def test_bsr3_block_jacobi(grid, n):
+    """Algorithm 7.1 with M = 3x3 block diagonal of A (right preconditioning) on the reservoir systems."""
+    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), precond=1, sensitive=True)
+
+
+@pytest.mark.parametrize("n", [1, 4])
+def test_csr_point_jacobi(n):
+    """Algorithm 7.1 with M = diag(A) on CSR systems (real and complex)."""
+    check_parity(workloads.config2(n=n, m=20, maxit=4000), precond=1)
+    check_parity(workloads.config5(n=n, m=12, maxit=4000), precond=1)
 
 
 @pytest.mark.parametrize("n", [4, 16])

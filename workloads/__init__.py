@@ -161,7 +161,7 @@ def helmholtz_3d(m: int, pe: float, k: float, gen: np.random.Generator, sigma: f
 
 
 def reservoir_bsr3(nx: int, ny: int, nz: int, gen: np.random.Generator, ln_sigma: float = 2.0,
-                   corr: float = 8.0):
+                   corr: float = 8.0, accum: float = 1e-2):
     """Block-diagonally-dominant nonsymmetric 3x3-block system on an nx*ny*nz grid.
 
     ln K = ln_sigma * Z with Z white noise Gaussian-filtered (std corr/sqrt(2)
@@ -170,7 +170,7 @@ def reservoir_bsr3(nx: int, ny: int, nz: int, gen: np.random.Generator, ln_sigma
     C = I + 0.2 E_C, U = 0.5 |E_U| (E seeded 3x3 normals) and theta_ab = 1 if
     b is upwind of a under a smooth seeded potential with a linear x trend.
     Diagonal block A_aa = sum_b T_ab (C + theta_ab U) + D_a with
-    D_a = (1e-2 mean_b T_ab + 1e-3) I.  Cells ordered x fastest.
+    D_a = (accum mean_b T_ab + 1e-3) I (an accumulation term).  Cells ordered x fastest.
     """
     shape = (nz, ny, nx)
     z = gen.standard_normal(shape)
@@ -214,7 +214,7 @@ def reservoir_bsr3(nx: int, ny: int, nz: int, gen: np.random.Generator, ln_sigma
             np.add.at(diag, a, blk)
             np.add.at(tsum, a, T)
             np.add.at(tcount, a, 1.0)
-    dshift = 1e-2 * tsum / np.maximum(tcount, 1.0) + 1e-3
+    dshift = accum * tsum / np.maximum(tcount, 1.0) + 1e-3
     diag += dshift[:, None, None] * np.eye(3)[None]
     brow.append(np.arange(ncell, dtype=np.int64))
     bcol.append(np.arange(ncell, dtype=np.int64))
@@ -295,10 +295,10 @@ def config2(n: int = 4, m: int = 128, maxit: int = 20000, velocity: str = "const
                    meta=dict(dims=3, m=m, pe=20.0))
 
 
-def config3(n: int = 8, grid=(60, 220, 85), maxit: int = 20000):
+def config3(n: int = 8, grid=(60, 220, 85), maxit: int = 20000, accum: float = 1e-2):
     """Reservoir-shaped 3x3-block system on a nx*ny*nz grid (BSR3)."""
     nx, ny, nz = grid
-    A = reservoir_bsr3(nx, ny, nz, rng(3, 0))
+    A = reservoir_bsr3(nx, ny, nz, rng(3, 0), accum=accum)
     N = A.shape[0]
     b = rng(3, 1).standard_normal(N)
     Q = _qblock(rng(3, 2), N, n)
