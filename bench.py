@@ -76,12 +76,94 @@ def cpu_baseline(p, iters_gpu, sample_iters):
                       f"scaled to the GPU's {iters_gpu} iterations"}
 
 
+def bench_serving(args, torch, workloads, binding):
+    """Continuous batching of a Poisson stream of uneven solves (fp32 inner / fp64 refinement, tol 1e-10)."""
+    reqs = workloads.serving_trace(count=args.requests)
+    t = time.perf_counter()
+    items = []
+    for k, r in enumerate(reqs):
+        p = workloads.serving_problem(r)
+        dA = binding.to_device(p.A)
+        b = torch.from_numpy(p.b).cuda()
+        x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+        Q = binding.column_major(p.Q)
+        items.append((r, p, dA, b, x, Q))
+        if (k + 1) % 100 == 0:
+            log(f"[bench] generated and uploaded {k + 1}/{len(reqs)} requests ({time.perf_counter() - t:.0f} s)")
+    torch.cuda.synchronize()
+    prec = binding.MLB_PREC_FP32_IR if args.serve_precision == "ir" else binding.MLB_PREC_FP64
+    # warm-up: one request alone (first-use costs of the kernels)
+    r0, p0, dA0, b0, x0, Q0 = items[0]
+    s = binding.Solver(dA0, p0.n, tol=p0.tol, maxit=p0.maxit, precision=prec)
+    s.solve(b0, x0, Q0)
+    s.close()
+    for it in items:
+        it[4].zero_()
+    torch.cuda.synchronize()
+
+    server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight)
+    t0 = time.perf_counter()
+    tickets = []
+    for r, p, dA, b, x, Q in items:
+        delay = t0 + r.arrival_s - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec))
+    lat, flags, errs, iters = [], [], [], []
+    for tk in tickets:
+        res, tim = server.wait(tk)
+        lat.append(tim.latency_ms)
+        flags.append(res.flag)
+        errs.append(res.err_true)
+        iters.append(res.iter)
+    makespan = time.perf_counter() - t0
+    st = server.stats()
+    server.close()
+    log(f"[bench] serving: {len(items)} requests in {makespan:.2f} s, peak concurrency {st.peak_running}, "
+        f"peak footprint {st.peak_used_bytes / 1e9:.2f} GB, max true residual {max(errs):.2e}")
+
+    # the same requests as plain fp64 solves, one after another
+    for it in items:
+        it[4].zero_()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seq_err = 0.0
+    for r, p, dA, b, x, Q in items:
+        s = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit)
+        res = s.solve(b, x, Q)
+        s.close()
+        seq_err = max(seq_err, res.err_true)
+    seq = time.perf_counter() - t1
+    log(f"[bench] sequential plain fp64: {seq:.2f} s, max true residual {seq_err:.2e}")
+    lat = np.array(lat)
+    return {
+        "metric": "batched solves/s", "value": len(items) / makespan, "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": 1e3 * makespan, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 inner / f64 refinement" if args.serve_precision == "ir" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving_poisson200_{len(items)}req", "requests": len(items),
+                   "arrival_rate_per_s": 200.0, "N_range": [int(min(r.N for r in reqs)), int(max(r.N for r in reqs))],
+                   "inflight": args.inflight, "budget_gb": args.budget_gb, "tol": 1e-10,
+                   "all_converged": bool(all(f == 0 for f in flags)), "max_err_true": float(max(errs)),
+                   "total_iterations": int(sum(iters))},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "peak_concurrency": int(st.peak_running), "peak_footprint_bytes": int(st.peak_used_bytes),
+        "sequential_fp64": {"seconds": seq, "solves_per_s": len(items) / seq, "max_err_true": seq_err},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "reservoir", "helmholtz"])
+    ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "reservoir", "helmholtz", "serving"])
+    ap.add_argument("--requests", type=int, default=400, help="serving: first requests of the seeded trace")
+    ap.add_argument("--inflight", type=int, default=8, help="serving: solves in flight")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM admission budget")
+    ap.add_argument("--serve-precision", default="fp64", choices=["fp64", "ir"],
+                    help="serving: iteration precision (fp32-IR doubles the iteration count on these systems)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "ir"])
     ap.add_argument("--n", type=int, default=0, help="number of shadow vectors (0 = the workload's)")
     ap.add_argument("--m", type=int, default=0, help="grid points per dimension (0 = the workload's)")
@@ -107,6 +189,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args, torch, workloads, binding)), flush=True)
+        return
     t = time.perf_counter()
     if args.workload == "convdiff3d":
         p = workloads.config2(n=args.n or 4, m=args.m or 128)

@@ -170,6 +170,68 @@ enum {
   MLB_KERNEL_COMBINE = 2      /* beta~ combination + F multi-dot                  */
 };
 
+/*
+ * Serving: continuous batching of whole solves (an addition of this library;
+ * the paper's setting is one solve at a time, or a sequence of systems in
+ * Section 5.2).
+ *
+ * A server owns max_inflight workers, each with its own HIP stream.  Requests
+ * are admitted first-in first-out: the oldest waiting request starts as soon
+ * as a worker is free and its device footprint (mlbicgstab_workspace_size)
+ * fits the unused part of budget_bytes.  Requests that arrive while others run
+ * therefore start as slots and memory free up, and their kernels overlap on
+ * the device.  A solve gives the same result as it would alone (same grids,
+ * same reduction order).  The caller's A arrays, b, x and Q of a request must
+ * stay allocated, and x untouched, until the request has been collected.
+ * Work is not ordered with any caller stream: the caller must have finished
+ * writing b, x and Q (e.g. synchronised its stream) before submitting.
+ */
+typedef struct mlb_server* mlb_server_handle;
+
+typedef struct {
+  uint64_t budget_bytes;    /* HBM admission budget for the requests' footprints */
+  int32_t max_inflight;     /* workers = solves in flight, 1..64              */
+} mlb_server_options;
+
+typedef struct {
+  double queued_ms;         /* submit -> start                                  */
+  double run_ms;            /* start -> completion                              */
+  double latency_ms;        /* submit -> completion                             */
+  uint64_t footprint_bytes; /* admitted footprint                               */
+} mlb_request_timing;
+
+typedef struct {
+  uint64_t budget_bytes, used_bytes, peak_used_bytes;
+  int64_t queued;
+  int32_t running, peak_running;
+  int64_t completed;
+} mlb_server_stats_t;
+
+/* Start the workers.  Returns 0 or an API error. */
+int mlb_server_create(const mlb_server_options* opt, mlb_server_handle* out);
+
+/*
+ * Queue one solve (same arguments as mlbicgstab_create + mlbicgstab_solve,
+ * with every device array borrowed until collection).  *ticket identifies it.
+ * MLB_ENOMEM if its footprint exceeds the whole budget.
+ */
+int mlb_server_submit(mlb_server_handle s, const mlb_matrix* A, const mlb_options* opt, const void* b, void* x,
+                      const void* Q, int64_t ldq, int64_t* ticket);
+
+/*
+ * Collect a request: poll returns 0 while it is pending; poll and wait return
+ * 1 once it has completed (res and timing filled, the ticket is then released),
+ * or the request's API error (<= -2).  The solve's own flag is in res->flag.
+ */
+int mlb_server_poll(mlb_server_handle s, int64_t ticket, mlb_result* res, mlb_request_timing* timing);
+int mlb_server_wait(mlb_server_handle s, int64_t ticket, mlb_result* res, mlb_request_timing* timing);
+
+/* Budget, peak footprint in flight, queue length, peak concurrency, completions. */
+int mlb_server_stats(mlb_server_handle s, mlb_server_stats_t* out);
+
+/* Finish every queued request, stop the workers and free the server. */
+int mlb_server_destroy(mlb_server_handle s);
+
 #ifdef __cplusplus
 }
 #endif

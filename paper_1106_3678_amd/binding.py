@@ -63,7 +63,33 @@ class mlb_result(ctypes.Structure):
     ]
 
 
+class mlb_server_options(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32)]
+
+
+class mlb_request_timing(ctypes.Structure):
+    _fields_ = [
+        ("queued_ms", ctypes.c_double),
+        ("run_ms", ctypes.c_double),
+        ("latency_ms", ctypes.c_double),
+        ("footprint_bytes", ctypes.c_uint64),
+    ]
+
+
+class mlb_server_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("budget_bytes", ctypes.c_uint64),
+        ("used_bytes", ctypes.c_uint64),
+        ("peak_used_bytes", ctypes.c_uint64),
+        ("queued", ctypes.c_int64),
+        ("running", ctypes.c_int32),
+        ("peak_running", ctypes.c_int32),
+        ("completed", ctypes.c_int64),
+    ]
+
+
 mlb_handle = ctypes.c_void_p
+mlb_server_handle = ctypes.c_void_p
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
@@ -84,6 +110,20 @@ _lib.mlbicgstab_last_error.argtypes = []
 _lib.mlbicgstab_last_error.restype = ctypes.c_char_p
 _lib.mlbicgstab_time_kernel.argtypes = [mlb_handle, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
 _lib.mlbicgstab_time_kernel.restype = ctypes.c_int
+_lib.mlb_server_create.argtypes = [ctypes.POINTER(mlb_server_options), ctypes.POINTER(mlb_server_handle)]
+_lib.mlb_server_create.restype = ctypes.c_int
+_lib.mlb_server_submit.argtypes = [mlb_server_handle, ctypes.POINTER(mlb_matrix), ctypes.POINTER(mlb_options),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64)]
+_lib.mlb_server_submit.restype = ctypes.c_int
+for _f in ("mlb_server_poll", "mlb_server_wait"):
+    getattr(_lib, _f).argtypes = [mlb_server_handle, ctypes.c_int64, ctypes.POINTER(mlb_result),
+                                  ctypes.POINTER(mlb_request_timing)]
+    getattr(_lib, _f).restype = ctypes.c_int
+_lib.mlb_server_stats.argtypes = [mlb_server_handle, ctypes.POINTER(mlb_server_stats_t)]
+_lib.mlb_server_stats.restype = ctypes.c_int
+_lib.mlb_server_destroy.argtypes = [mlb_server_handle]
+_lib.mlb_server_destroy.restype = ctypes.c_int
 
 
 class MlbError(RuntimeError):
@@ -132,6 +172,43 @@ def mlbicgstab_time_kernel(h, kernel: int, reps: int) -> float:
     ms = ctypes.c_double()
     _check(_lib.mlbicgstab_time_kernel(h, kernel, reps, ctypes.byref(ms)))
     return ms.value
+
+
+def mlb_server_create(budget_bytes: int, max_inflight: int):
+    h = mlb_server_handle()
+    _check(_lib.mlb_server_create(ctypes.byref(mlb_server_options(budget_bytes, max_inflight)), ctypes.byref(h)))
+    return h
+
+
+def mlb_server_submit(s, A: mlb_matrix, opt: mlb_options, b_ptr: int, x_ptr: int, q_ptr: int, ldq: int) -> int:
+    t = ctypes.c_int64()
+    _check(_lib.mlb_server_submit(s, ctypes.byref(A), ctypes.byref(opt), ctypes.c_void_p(b_ptr),
+                                  ctypes.c_void_p(x_ptr), ctypes.c_void_p(q_ptr), ctypes.c_int64(ldq),
+                                  ctypes.byref(t)))
+    return t.value
+
+
+def mlb_server_poll(s, ticket: int):
+    """(done, result, timing); done False while pending."""
+    res, tim = mlb_result(), mlb_request_timing()
+    rc = _check(_lib.mlb_server_poll(s, ticket, ctypes.byref(res), ctypes.byref(tim)))
+    return rc == 1, res, tim
+
+
+def mlb_server_wait(s, ticket: int):
+    res, tim = mlb_result(), mlb_request_timing()
+    _check(_lib.mlb_server_wait(s, ticket, ctypes.byref(res), ctypes.byref(tim)))
+    return res, tim
+
+
+def mlb_server_stats(s) -> mlb_server_stats_t:
+    st = mlb_server_stats_t()
+    _check(_lib.mlb_server_stats(s, ctypes.byref(st)))
+    return st
+
+
+def mlb_server_destroy(s) -> int:
+    return _check(_lib.mlb_server_destroy(s))
 
 
 def raw_call(name, *args):
@@ -223,6 +300,52 @@ class Solver:
         if self.h:
             mlbicgstab_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching front end: submit() solves, wait()/poll() for their results."""
+
+    def __init__(self, budget_bytes: int, max_inflight: int = 4):
+        self.h = mlb_server_create(budget_bytes, max_inflight)
+        self._keep = {}
+
+    def submit(self, dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
+               precision: int = MLB_PREC_FP64, inner_tol: float = 0.0, precond: int = MLB_PRECOND_NONE) -> int:
+        N = dmat.nrows
+        if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != n or Q.stride(0) != 1:
+            raise ValueError("Q must be an N x n column-major tensor")
+        opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, 0, 0, None, precond)
+        ldq = Q.stride(1) if n > 1 else N
+        t = mlb_server_submit(self.h, dmat.descriptor(), opt, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
+        self._keep[t] = (dmat, b, x, Q)
+        return t
+
+    def wait(self, ticket: int):
+        try:
+            return mlb_server_wait(self.h, ticket)
+        finally:
+            self._keep.pop(ticket, None)
+
+    def poll(self, ticket: int):
+        done, res, tim = mlb_server_poll(self.h, ticket)
+        if done:
+            self._keep.pop(ticket, None)
+        return done, res, tim
+
+    def stats(self) -> mlb_server_stats_t:
+        return mlb_server_stats(self.h)
+
+    def close(self):
+        if self.h:
+            mlb_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -12,7 +12,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -40,22 +46,31 @@ struct Error {
     if (e_ != hipSuccess) throw Error{MLB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
   } while (0)
 
-// Device allocations owned by one solver, freed together.
+// Device allocations owned by one solver, freed together.  Stream-ordered mode
+// (hipMallocAsync / hipFreeAsync on one stream) is used by the serving path, so
+// that admitting or retiring a request never synchronises the whole device.
 struct Allocs {
   std::vector<void*> ptrs;
+  hipStream_t stream = nullptr;
+  bool ordered = false;
+  Allocs() = default;
+  Allocs(hipStream_t s, bool ord) : stream(s), ordered(ord) {}
+  Allocs(const Allocs&) = delete;
+  Allocs& operator=(const Allocs&) = delete;
   template <class T>
   T* get(size_t count) {
     void* p = nullptr;
     if (count == 0) count = 1;
-    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    const hipError_t e = ordered ? hipMallocAsync(&p, count * sizeof(T), stream) : hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
       (void)hipGetLastError();
-      throw Error{MLB_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+      throw Error{MLB_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed"};
     }
     ptrs.push_back(p);
     return (T*)p;
   }
   ~Allocs() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) (void)(ordered ? hipFreeAsync(p, stream) : hipFree(p));
   }
 };
 
@@ -128,7 +143,7 @@ static Mat<V> build_transpose(const Mat<V>& A, Allocs& al, hipStream_t s) {
   int* rpT = al.get<int>(m + 1);
   int* ciT = al.get<int>(A.nnz);
   V* valT = al.get<V>((size_t)A.nnz * bs);
-  Allocs tmp;
+  Allocs tmp(al.stream, al.ordered);
   int* cnt = tmp.get<int>(m);
   int* fill = tmp.get<int>(m);
   HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int) * m, s));
@@ -252,7 +267,11 @@ struct Engine {
   const V* Q = nullptr;
   long long ldq = 0;
 
-  void init(const Mat<V>& A_, const Mat<V>& AH_, int n_, hipStream_t s_, Allocs& al) {
+  bool own_flag = true;
+
+  // ext_flag: a pinned, host-mapped int the caller owns (serving workers reuse one
+  // per worker); NULL = allocate one.
+  void init(const Mat<V>& A_, const Mat<V>& AH_, int n_, hipStream_t s_, Allocs& al, int* ext_flag = nullptr) {
     A = A_;
     AH = AH_;
     N = A.nrows;
@@ -282,13 +301,18 @@ struct Engine {
     grid_vec = grid_for(N, std::min(MAX_GRID, 8 * cus));
     grid_spmv = grid_for(A.nbrows, std::min(MAX_GRID, occ * cus));
     part = al.get<Sc>((size_t)std::max(grid_vec, grid_spmv) * (NMAX + 1));
-    HIP_TRY(hipHostMalloc((void**)&host_done, sizeof(int), hipHostMallocMapped));
+    if (ext_flag) {
+      host_done = ext_flag;
+      own_flag = false;
+    } else {
+      HIP_TRY(hipHostMalloc((void**)&host_done, sizeof(int), hipHostMallocMapped));
+    }
     *host_done = 0;
     HIP_TRY(hipHostGetDevicePointer((void**)&host_done_dev, host_done, 0));
     for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   void release() {
-    if (host_done) (void)hipHostFree(host_done);
+    if (host_done && own_flag) (void)hipHostFree(host_done);
     host_done = nullptr;
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -543,6 +567,7 @@ struct mlb_solver {
   hipStream_t s = nullptr;
   bool own_stream = false;
   bool solved = false;
+  int* ext_flags = nullptr;   // two pinned host-mapped ints owned by a serving worker, or NULL
   Allocs al;
   std::unique_ptr<Impl<double, float>> real;
   std::unique_ptr<Impl<cplx<double>, cplx<float>>> cpx;
@@ -610,7 +635,7 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
     im.Mblk = h->al.get<V64>((size_t)A.nbrows * b2);
     im.Minv = h->al.get<V64>((size_t)A.nbrows * b2);
     V64* scaled = h->al.get<V64>((size_t)A.nnz * b2);
-    Allocs tmp;
+    Allocs tmp(h->al.stream, h->al.ordered);
     int* bad = tmp.get<int>(1);
     HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), h->s));
     const int g = grid_for(A.nbrows, 4096);
@@ -630,7 +655,7 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
     A.val = scaled;
   }
   Mat<V64> AH = build_transpose(A, h->al, h->s);
-  im.e64.init(A, AH, h->opt.n, h->s, h->al);
+  im.e64.init(A, AH, h->opt.n, h->s, h->al, h->ext_flags);
   im.r64 = h->al.get<V64>(h->N);
   if (h->opt.precision == MLB_PREC_FP32_IR) {
     const int bs = A.format == MLB_BSR3 ? 9 : 1;
@@ -654,7 +679,7 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
     AH32.val = vt;
     A32.lpr = A.lpr;
     AH32.lpr = AH.lpr;
-    im.e32.init(A32, AH32, h->opt.n, h->s, h->al);
+    im.e32.init(A32, AH32, h->opt.n, h->s, h->al, h->ext_flags ? h->ext_flags + 1 : nullptr);
     im.has32 = true;
     im.b32 = h->al.get<V32>(h->N);
     im.x32 = h->al.get<V32>(h->N);
@@ -802,7 +827,7 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
 // requested kernel's launches are bracketed by HIP event pairs.
 template <class V>
 static double time_kernel_impl(Engine<V>& e, int kernel, int reps) {
-  Allocs tmp;
+  Allocs tmp(e.s, false);
   V* xs = tmp.get<V>(e.N);   // scratch iterate (the caller's x is not touched)
   HIP_TRY(hipMemsetAsync(xs, 0, sizeof(V) * e.N, e.s));
   std::vector<hipEvent_t> evs;
@@ -852,6 +877,67 @@ static int guarded(F&& f) {
   }
 }
 
+// Validates A and opt, builds A^H (and the preconditioned / fp32 copies) and the
+// workspace.  ordered: stream-ordered allocations on `stream` (serving);
+// flags: two pinned host-mapped ints for the engines' done flags, or NULL.
+static std::unique_ptr<mlb_solver> create_solver(const mlb_matrix* A, const mlb_options* opt, hipStream_t stream,
+                                                 bool ordered, int* flags) {
+  check_matrix(A);
+  check_options(opt);
+  auto h = std::make_unique<mlb_solver>();
+  h->dtype = A->dtype;
+  h->format = A->format;
+  h->N = (int)A->nrows;
+  h->opt = *opt;
+  // NULL is the legacy default stream: work stays ordered with everything else
+  // the caller enqueued there (e.g. the fill that zeroes x before a solve).
+  h->s = stream;
+  h->al.stream = stream;
+  h->al.ordered = ordered;
+  h->ext_flags = flags;
+  // validate the index arrays on the device before any kernel relies on them
+  {
+    Allocs tmp(stream, ordered);
+    int* bad = tmp.get<int>(1);
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), h->s));
+    const int nbr = A->format == MLB_BSR3 ? (int)(A->nrows / 3) : (int)A->nrows;
+    k_validate<<<grid_for(std::max<long long>(nbr + 1, A->nnz), 4096), BLOCK, 0, h->s>>>(A->row_ptr, A->col_idx, nbr,
+                                                                                         A->nnz, nbr, bad);
+    HIP_TRY(hipGetLastError());
+    int hb = 0;
+    HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipStreamSynchronize(h->s));
+    if (hb) {
+      std::string why;
+      if (hb & 1) why += " row_ptr[0] != 0;";
+      if (hb & 2) why += " row_ptr[last] != nnz;";
+      if (hb & 4) why += " row_ptr decreases;";
+      if (hb & 8) why += " col_idx out of range;";
+      throw Error{MLB_EINVAL, "invalid matrix:" + why};
+    }
+  }
+  if (A->dtype == MLB_R64) {
+    h->real = std::make_unique<Impl<double, float>>();
+    create_impl(h.get(), A, *h->real);
+  } else {
+    h->cpx = std::make_unique<Impl<cplx<double>, cplx<float>>>();
+    create_impl(h.get(), A, *h->cpx);
+  }
+  return h;
+}
+
+static int solve_solver(mlb_solver* h, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res) {
+  if (!b || !x || !Q) throw Error{MLB_EINVAL, "b, x and Q must be device pointers"};
+  if (ldq < h->N) throw Error{MLB_EINVAL, "ldq must be >= N"};
+  int rc;
+  if (h->real)
+    rc = solve_impl(h, *h->real, (const double*)b, (double*)x, (const double*)Q, ldq, res);
+  else
+    rc = solve_impl(h, *h->cpx, (const cplx<double>*)b, (cplx<double>*)x, (const cplx<double>*)Q, ldq, res);
+  h->solved = true;
+  return rc;
+}
+
 }  // namespace mlb
 
 // ------------------------------------------------------------------ C ABI
@@ -888,45 +974,7 @@ int mlbicgstab_create(const mlb_matrix* A, const mlb_options* opt, void* hip_str
   if (out) *out = nullptr;
   return guarded([&]() -> int {
     if (!out) throw Error{MLB_EINVAL, "out pointer is NULL"};
-    check_matrix(A);
-    check_options(opt);
-    auto h = std::make_unique<mlb_solver>();
-    h->dtype = A->dtype;
-    h->format = A->format;
-    h->N = (int)A->nrows;
-    h->opt = *opt;
-    // NULL is the legacy default stream: work stays ordered with everything else
-    // the caller enqueued there (e.g. the fill that zeroes x before a solve).
-    h->s = (hipStream_t)hip_stream;
-    // validate the index arrays on the device before any kernel relies on them
-    {
-      Allocs tmp;
-      int* bad = tmp.get<int>(1);
-      HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), h->s));
-      const int nbr = A->format == MLB_BSR3 ? (int)(A->nrows / 3) : (int)A->nrows;
-      k_validate<<<grid_for(std::max<long long>(nbr + 1, A->nnz), 4096), BLOCK, 0, h->s>>>(
-          A->row_ptr, A->col_idx, nbr, A->nnz, nbr, bad);
-      HIP_TRY(hipGetLastError());
-      int hb = 0;
-      HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->s));
-      HIP_TRY(hipStreamSynchronize(h->s));
-      if (hb) {
-        std::string why;
-        if (hb & 1) why += " row_ptr[0] != 0;";
-        if (hb & 2) why += " row_ptr[last] != nnz;";
-        if (hb & 4) why += " row_ptr decreases;";
-        if (hb & 8) why += " col_idx out of range;";
-        throw Error{MLB_EINVAL, "invalid matrix:" + why};
-      }
-    }
-    if (A->dtype == MLB_R64) {
-      h->real = std::make_unique<Impl<double, float>>();
-      create_impl(h.get(), A, *h->real);
-    } else {
-      h->cpx = std::make_unique<Impl<cplx<double>, cplx<float>>>();
-      create_impl(h.get(), A, *h->cpx);
-    }
-    *out = h.release();
+    *out = create_solver(A, opt, (hipStream_t)hip_stream, false, nullptr).release();
     return 0;
   });
 }
@@ -934,15 +982,7 @@ int mlbicgstab_create(const mlb_matrix* A, const mlb_options* opt, void* hip_str
 int mlbicgstab_solve(mlb_handle h, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res) {
   return guarded([&]() -> int {
     if (!h) throw Error{MLB_EINVAL, "handle is NULL"};
-    if (!b || !x || !Q) throw Error{MLB_EINVAL, "b, x and Q must be device pointers"};
-    if (ldq < h->N) throw Error{MLB_EINVAL, "ldq must be >= N"};
-    int rc;
-    if (h->real)
-      rc = solve_impl(h, *h->real, (const double*)b, (double*)x, (const double*)Q, ldq, res);
-    else
-      rc = solve_impl(h, *h->cpx, (const cplx<double>*)b, (cplx<double>*)x, (const cplx<double>*)Q, ldq, res);
-    h->solved = true;
-    return rc;
+    return solve_solver(h, b, x, Q, ldq, res);
   });
 }
 
@@ -968,6 +1008,251 @@ int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* m
       *ms_per_launch = ir ? time_kernel_impl(h->real->e32, kernel, reps) : time_kernel_impl(h->real->e64, kernel, reps);
     else
       *ms_per_launch = ir ? time_kernel_impl(h->cpx->e32, kernel, reps) : time_kernel_impl(h->cpx->e64, kernel, reps);
+    return 0;
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ serving
+//
+// Continuous batching of whole solves.  Requests wait in a FIFO queue; each of
+// max_inflight workers owns a HIP stream (non-blocking, default priority) and a
+// pinned done-flag pair.  A worker takes the head request as soon as it is free
+// and the request's device footprint (mlbicgstab_workspace_size) fits the
+// unused part of the HBM budget, then runs create -> solve -> destroy on its
+// stream with stream-ordered allocations.  Requests that arrive while others
+// run are admitted as slots and memory free up; their kernels overlap on the
+// device.  Every solve uses the same grids and reduction order as it would
+// alone, so its result does not depend on what else is running.
+
+namespace mlb {
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  int64_t ticket = 0;
+  mlb_matrix A{};
+  mlb_options opt{};
+  const void* b = nullptr;
+  void* x = nullptr;
+  const void* Q = nullptr;
+  int64_t ldq = 0;
+  size_t footprint = 0;
+  double t_submit = 0, t_start = 0, t_done = 0;
+  mlb_result res{};
+  int rc = 0;
+  std::string err;
+  bool done = false;
+};
+
+struct Server {
+  size_t budget = 0, used = 0, peak = 0;
+  int max_inflight = 1;
+  int device = 0;
+  int running = 0, peak_running = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<int64_t, std::shared_ptr<Request>> table;
+  int64_t next_ticket = 1;
+  int64_t completed = 0;
+  bool stopping = false;
+  std::vector<std::thread> workers;
+  std::string init_error;
+};
+
+static void run_request(Request& r, hipStream_t st, int* flags) {
+  try {
+    auto h = create_solver(&r.A, &r.opt, st, true, flags);
+    r.rc = solve_solver(h.get(), r.b, r.x, r.Q, r.ldq, &r.res);
+    HIP_TRY(hipStreamSynchronize(st));
+    h.reset();
+    HIP_TRY(hipStreamSynchronize(st));
+  } catch (const Error& e) {
+    r.rc = e.code;
+    r.err = e.msg;
+  } catch (const std::exception& e) {
+    r.rc = MLB_EHIP;
+    r.err = e.what();
+  }
+}
+
+static void worker_main(Server* S) {
+  hipStream_t st = nullptr;
+  int* flags = nullptr;
+  bool ok = hipSetDevice(S->device) == hipSuccess && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+            hipHostMalloc((void**)&flags, 2 * sizeof(int), hipHostMallocMapped) == hipSuccess;
+  while (true) {
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] {
+        return (S->stopping && S->queue.empty()) ||
+               (!S->queue.empty() && S->used + S->queue.front()->footprint <= S->budget);
+      });
+      if (S->queue.empty()) break;   // stopping and drained
+      r = S->queue.front();
+      S->queue.pop_front();
+      S->used += r->footprint;
+      S->peak = std::max(S->peak, S->used);
+      S->running++;
+      S->peak_running = std::max(S->peak_running, S->running);
+      r->t_start = now_s();
+    }
+    S->cv_work.notify_all();   // the next head may fit too
+    if (ok) {
+      run_request(*r, st, flags);
+    } else {
+      r->rc = MLB_EHIP;
+      r->err = "serving worker could not create its stream or pinned flags";
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      r->t_done = now_s();
+      r->done = true;
+      S->used -= r->footprint;
+      S->running--;
+      S->completed++;
+    }
+    S->cv_work.notify_all();
+    S->cv_done.notify_all();
+  }
+  if (flags) (void)hipHostFree(flags);
+  if (st) (void)hipStreamDestroy(st);
+}
+
+static void fill_timing(const Request& r, mlb_request_timing* t) {
+  if (!t) return;
+  t->queued_ms = 1e3 * (r.t_start - r.t_submit);
+  t->run_ms = 1e3 * (r.t_done - r.t_start);
+  t->latency_ms = 1e3 * (r.t_done - r.t_submit);
+  t->footprint_bytes = r.footprint;
+}
+
+}  // namespace mlb
+
+struct mlb_server : mlb::Server {};
+
+extern "C" {
+
+int mlb_server_create(const mlb_server_options* o, mlb_server_handle* out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> int {
+    if (!o || !out) throw Error{MLB_EINVAL, "options and out must be non-NULL"};
+    if (o->budget_bytes == 0) throw Error{MLB_EINVAL, "budget_bytes must be > 0"};
+    if (o->max_inflight < 1 || o->max_inflight > 64) throw Error{MLB_EINVAL, "max_inflight must be in [1, 64]"};
+    auto S = std::make_unique<mlb_server>();
+    S->budget = o->budget_bytes;
+    S->max_inflight = o->max_inflight;
+    HIP_TRY(hipGetDevice(&S->device));
+    // keep freed stream-ordered memory cached in the pool between requests
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    for (int w = 0; w < o->max_inflight; ++w) S->workers.emplace_back(worker_main, S.get());
+    *out = S.release();
+    return 0;
+  });
+}
+
+int mlb_server_submit(mlb_server_handle S, const mlb_matrix* A, const mlb_options* opt, const void* b, void* x,
+                      const void* Q, int64_t ldq, int64_t* ticket) {
+  return guarded([&]() -> int {
+    if (!S || !ticket) throw Error{MLB_EINVAL, "server and ticket must be non-NULL"};
+    check_matrix(A);
+    check_options(opt);
+    if (!b || !x || !Q) throw Error{MLB_EINVAL, "b, x and Q must be device pointers"};
+    if (ldq < A->nrows) throw Error{MLB_EINVAL, "ldq must be >= N"};
+    auto r = std::make_shared<Request>();
+    r->A = *A;
+    r->opt = *opt;
+    r->b = b;
+    r->x = x;
+    r->Q = Q;
+    r->ldq = ldq;
+    size_t fp = 0;
+    int rc = mlbicgstab_workspace_size(A, opt, &fp);
+    if (rc != 0) throw Error{rc, g_last_error};
+    r->footprint = fp;
+    if (fp > S->budget) throw Error{MLB_ENOMEM, "request footprint exceeds the server's HBM budget"};
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->stopping) throw Error{MLB_EINVAL, "server is shutting down"};
+      r->ticket = S->next_ticket++;
+      r->t_submit = now_s();
+      S->table[r->ticket] = r;
+      S->queue.push_back(r);
+      *ticket = r->ticket;
+    }
+    S->cv_work.notify_all();
+    return 0;
+  });
+}
+
+static int collect(mlb_server_handle S, int64_t ticket, mlb_result* res, mlb_request_timing* t, bool block) {
+  std::shared_ptr<Request> r;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->table.find(ticket);
+    if (it == S->table.end()) throw Error{MLB_EINVAL, "unknown or already collected ticket"};
+    r = it->second;
+    if (!r->done) {
+      if (!block) return 0;
+      S->cv_done.wait(lk, [&] { return r->done; });
+    }
+    S->table.erase(ticket);
+  }
+  if (res) *res = r->res;
+  fill_timing(*r, t);
+  if (r->rc <= -2) throw Error{r->rc, r->err};
+  return 1;
+}
+
+int mlb_server_poll(mlb_server_handle S, int64_t ticket, mlb_result* res, mlb_request_timing* t) {
+  return guarded([&]() -> int {
+    if (!S) throw Error{MLB_EINVAL, "server is NULL"};
+    return collect(S, ticket, res, t, false);
+  });
+}
+
+int mlb_server_wait(mlb_server_handle S, int64_t ticket, mlb_result* res, mlb_request_timing* t) {
+  return guarded([&]() -> int {
+    if (!S) throw Error{MLB_EINVAL, "server is NULL"};
+    return collect(S, ticket, res, t, true);
+  });
+}
+
+int mlb_server_stats(mlb_server_handle S, mlb_server_stats_t* st) {
+  return guarded([&]() -> int {
+    if (!S || !st) throw Error{MLB_EINVAL, "server and stats must be non-NULL"};
+    std::lock_guard<std::mutex> lk(S->mu);
+    st->budget_bytes = S->budget;
+    st->used_bytes = S->used;
+    st->peak_used_bytes = S->peak;
+    st->queued = (int64_t)S->queue.size();
+    st->running = S->running;
+    st->peak_running = S->peak_running;
+    st->completed = S->completed;
+    return 0;
+  });
+}
+
+int mlb_server_destroy(mlb_server_handle S) {
+  return guarded([&]() -> int {
+    if (!S) return 0;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stopping = true;
+    }
+    S->cv_work.notify_all();
+    for (auto& w : S->workers) w.join();
+    delete S;
     return 0;
   });
 }

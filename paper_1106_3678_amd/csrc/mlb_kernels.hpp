@@ -26,6 +26,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "mlb_types.hpp"
 
 namespace mlb {

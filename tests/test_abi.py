@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "mlbicgstab.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mlbicgstab_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mlb(?:icgstab)?_\w+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +29,8 @@ def binding():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("mlbicgstab_create", "mlbicgstab_solve", "mlbicgstab_destroy", "mlbicgstab_workspace_size",
-              "mlbicgstab_last_error", "mlbicgstab_time_kernel"):
+              "mlbicgstab_last_error", "mlbicgstab_time_kernel", "mlb_server_create", "mlb_server_submit",
+              "mlb_server_poll", "mlb_server_wait", "mlb_server_stats", "mlb_server_destroy"):
         assert f in names
 
 
@@ -94,3 +95,12 @@ def test_workspace_size_model(binding):
     assert s2 > s1 and s3 > 1.9 * s1
     # 3 vectors (G, W, F) per extra shadow vector, 8 bytes each
     assert abs((s2 - s1) - 4 * 3 * 30000 * 8) < 1024
+
+
+def test_server_rejects_bad_options(binding):
+    h = binding.mlb_server_handle()
+    for budget, inflight in [(0, 4), (1 << 30, 0), (1 << 30, 65)]:
+        o = binding.mlb_server_options(budget, inflight)
+        assert binding.raw_call("mlb_server_create", ctypes.byref(o), ctypes.byref(h)) == binding.MLB_EINVAL
+        assert h.value is None
+    assert binding.raw_call("mlb_server_destroy", None) == 0

@@ -1,0 +1,132 @@
+"""Serving (continuous batching through mlb_server_*): every result in a concurrent mix equals the same
+solve run alone, a failing request is isolated, and admission respects the HBM budget."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads
+from tests.gpu_util import gpu_available, rel
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import torch  # noqa: E402
+
+from paper_1106_3678_amd import binding  # noqa: E402
+
+
+def requests(count=14, seed=5):
+    """Uneven solves: 2D/3D convection-diffusion of different sizes, n in {2, 4, 8}, fp64 and fp32-IR."""
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        dims = 2 + (i % 2)
+        m = int(g.integers(12, 70)) if dims == 2 else int(g.integers(8, 22))
+        req = workloads.Request(i, 0.0, dims, m, float(g.uniform(0.5, 30)), int(g.choice([2, 4, 8])), 500 + i)
+        p = workloads.serving_problem(req, maxit=5000)
+        out.append((p, binding.MLB_PREC_FP32_IR if i % 3 == 0 else binding.MLB_PREC_FP64))
+    return out
+
+
+def upload(p):
+    dA = binding.to_device(p.A)
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    Q = binding.column_major(p.Q)
+    return dA, b, x, Q
+
+
+def solve_alone(p, prec):
+    dA, b, x, Q = upload(p)
+    s = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
+    res = s.solve(b, x, Q)
+    s.close()
+    return res, x.cpu().numpy()
+
+
+def test_mix_equals_alone():
+    reqs = requests()
+    alone = [solve_alone(p, prec) for p, prec in reqs]
+    server = binding.Server(budget_bytes=8 << 30, max_inflight=4)
+    bufs = [upload(p) for p, _ in reqs]
+    torch.cuda.synchronize()
+    tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
+               for (p, prec), (dA, b, x, Q) in zip(reqs, bufs)]
+    results = [server.wait(t) for t in tickets]
+    st = server.stats()
+    server.close()
+    print(f"peak concurrency {st.peak_running}, peak footprint {st.peak_used_bytes / 1e6:.1f} MB, "
+          f"completed {st.completed}", flush=True)
+    assert st.completed == len(reqs)
+    for k, ((p, prec), (res_a, x_a), (res_m, tim), (_, _, x_m, _)) in enumerate(zip(reqs, alone, results, bufs)):
+        xm = x_m.cpu().numpy()
+        print(f"{p.name} prec={prec}: alone flag={res_a.flag} iter={res_a.iter} | mix flag={res_m.flag} "
+              f"iter={res_m.iter} true={res_m.err_true:.2e} latency={tim.latency_ms:.1f} ms", flush=True)
+        assert res_m.flag == res_a.flag == 0
+        assert res_m.iter == res_a.iter
+        assert np.array_equal(xm, x_a), k
+        assert oracle.true_error(p.A, xm, p.b) < p.tol
+
+
+def test_failing_request_is_isolated():
+    """A breakdown (c_0 = 0) in the mix completes with flag -1 and does not disturb the others."""
+    reqs = requests(count=4, seed=9)
+    A = sp.csr_matrix(np.eye(3))
+    bad = workloads.Problem("c0", A, np.array([1.0, 0, 0]), np.array([[0.0], [1.0], [0.0]]), np.zeros(3), 1,
+                            1e-10, 10)
+    server = binding.Server(budget_bytes=4 << 30, max_inflight=3)
+    items = [(bad, binding.MLB_PREC_FP64)] + reqs
+    bufs = [upload(p) for p, _ in items]
+    torch.cuda.synchronize()
+    tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
+               for (p, prec), (dA, b, x, Q) in zip(items, bufs)]
+    results = [server.wait(t) for t in tickets]
+    server.close()
+    assert results[0][0].flag == -1 and results[0][0].iter == 0
+    for (p, prec), (res, _), (_, _, x, _) in zip(items[1:], results[1:], bufs[1:]):
+        res_a, x_a = solve_alone(p, prec)
+        assert res.flag == 0 and np.array_equal(x.cpu().numpy(), x_a)
+
+
+def test_admission_respects_budget():
+    """With a budget that fits about two requests, the footprint in flight never exceeds it."""
+    reqs = requests(count=8, seed=13)
+    bufs = [upload(p) for p, _ in reqs]
+    fps = []
+    for (p, prec), (dA, _, _, _) in zip(reqs, bufs):
+        opt = binding.mlb_options(p.n, p.tol, p.maxit, 0.0, prec, 0.0, 0, 0, None, 0)
+        fps.append(binding.mlbicgstab_workspace_size(dA.descriptor(), opt))
+    budget = int(sorted(fps)[-1] + sorted(fps)[-2])
+    server = binding.Server(budget_bytes=budget, max_inflight=6)
+    torch.cuda.synchronize()
+    tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
+               for (p, prec), (dA, b, x, Q) in zip(reqs, bufs)]
+    results = [server.wait(t) for t in tickets]
+    st = server.stats()
+    server.close()
+    assert all(r.flag == 0 for r, _ in results)
+    assert st.peak_used_bytes <= budget
+    # an oversize request is refused at submission
+    server = binding.Server(budget_bytes=1024, max_inflight=1)
+    p, prec = reqs[-1]
+    dA, b, x, Q = bufs[-1]
+    with pytest.raises(binding.MlbError) as e:
+        server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
+    assert e.value.code == binding.MLB_ENOMEM
+    server.close()
+
+
+def test_one_request_matches_oracle():
+    p, prec = requests(count=2, seed=21)[1]
+    server = binding.Server(budget_bytes=1 << 30, max_inflight=2)
+    dA, b, x, Q = upload(p)
+    torch.cuda.synchronize()
+    res, _ = server.wait(server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=binding.MLB_PREC_FP64))
+    server.close()
+    o = oracle.mlbicgstabt(p.A, p.b, p.Q, tol=p.tol, maxit=p.maxit)
+    assert res.flag == o.flag == 0
+    assert abs(res.iter - o.iter) <= max(1, int(0.05 * o.iter))
+    assert rel(x.cpu().numpy(), o.x) < 1e-6
