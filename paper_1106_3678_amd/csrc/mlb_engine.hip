@@ -87,7 +87,7 @@ static int max_grid() {
   static const int g = [] {
     const char* v = getenv("MLB_MAX_GRID");
     const int x = v ? atoi(v) : 0;
-    return x >= 64 && x <= 65536 ? x : 2048;
+    return x >= 64 && x <= MAX_PARTIAL_ROWS ? x : MAX_PARTIAL_ROWS;
   }();
   return g;
 }

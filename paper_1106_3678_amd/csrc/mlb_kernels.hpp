@@ -33,6 +33,7 @@
 namespace mlb {
 
 constexpr int NMAX = 32;        // largest n
+constexpr int MAX_PARTIAL_ROWS = 2048;   // most workgroups of a reducing pass
 constexpr int BLOCK = 256;      // threads per workgroup (4 waves of 64)
 constexpr int WAVE = 64;
 
@@ -93,6 +94,37 @@ __device__ inline void add_(double& a, double b) { a += b; }
 __device__ inline void add_(float& a, float b) { a += b; }
 template <class R>
 __device__ inline void add_(cplx<R>& a, cplx<R> b) { a.re += b.re; a.im += b.im; }
+
+// Sum over aligned groups of G = 4 or 8 lanes with DPP moves (VALU only):
+// quad permutes for lane ^ 1 and lane ^ 2, then the half-row mirror (lane i
+// of an 8-lane half-row takes lane 7 - i, which lies in the other quad).
+// Every lane of the group ends with the group's sum, added in a fixed order.
+template <int CTRL>
+__device__ inline float dpp_(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ inline double dpp_(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, class R>
+__device__ inline cplx<R> dpp_(cplx<R> v) {
+  return {dpp_<CTRL>(v.re), dpp_<CTRL>(v.im)};
+}
+constexpr int DPP_XOR1 = 0xB1;       // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;       // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+
+template <int G, class T>
+__device__ inline T group_sum(T v) {
+  static_assert(G == 4 || G == 8, "DPP group sums cover 4 or 8 lanes");
+  add_(v, dpp_<DPP_XOR1>(v));
+  add_(v, dpp_<DPP_XOR2>(v));
+  if constexpr (G == 8) add_(v, dpp_<DPP_HALF_MIRROR>(v));
+  return v;
+}
 
 template <class T>
 __device__ inline T wave_sum(T v) {
@@ -268,11 +300,42 @@ __global__ __launch_bounds__(BLOCK) void k_scalar(State<Sc>* st, const Sc* __res
   Sc acc[STRIDE];
 #pragma unroll
   for (int d = 0; d < STRIDE; ++d) acc[d] = zero<Sc>();
-  for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
-    const Sc* row = partial + (size_t)b * STRIDE;
+  // up to MAX_PARTIAL_ROWS producer workgroups: a fixed trip count lets every
+  // load of a lane be in flight at once (the order of the sums stays fixed)
+  constexpr int KR = MAX_PARTIAL_ROWS / BLOCK;                  // rows per lane
+  // rows loaded together: as many as fit in a budget of 64 eight-byte registers per lane
+  constexpr int WORDS = (int)(STRIDE * sizeof(Sc) / 8);
+  constexpr int KC = WORDS <= 8 ? KR : WORDS <= 16 ? 4 : 2;
+  if constexpr (WORDS > 32) {
+    // long rows (complex, large n): the accumulators alone take half the
+    // register file, so each row is summed as it arrives
+    for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
+      const Sc* row = partial + (size_t)b * STRIDE;
 #pragma unroll
-    for (int d = 0; d < STRIDE; ++d)
-      if (d < nsum) add_(acc[d], row[d]);
+      for (int d = 0; d < STRIDE; ++d)
+        if (d < nsum) add_(acc[d], row[d]);
+    }
+  } else {
+#pragma unroll
+  for (int k0 = 0; k0 < KR; k0 += KC) {
+    Sc v[KC][STRIDE];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int b = threadIdx.x + (k0 + k) * BLOCK;
+      // rows past nblocks re-read row 0 and entries past nsum are read unused:
+      // the buffer holds STRIDE entries for every producer workgroup
+      const Sc* row = partial + (size_t)(b < nblocks ? b : 0) * STRIDE;
+#pragma unroll
+      for (int d = 0; d < STRIDE; ++d) v[k][d] = row[d];
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const bool on = threadIdx.x + (k0 + k) * BLOCK < nblocks;
+#pragma unroll
+      for (int d = 0; d < STRIDE; ++d)
+        if (on && d < nsum) add_(acc[d], v[k][d]);
+    }
+  }
   }
 #pragma unroll
   for (int d = 0; d < STRIDE; ++d) {
@@ -479,6 +542,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csrw(State<Sc>* st, Sc* partial,
   const int lane = threadIdx.x % WAVE;
   const int sub = lane % LPR, grp = lane / LPR;
   const int nwt = (a.nrows + WAVE - 1) / WAVE;                 // wave tiles
+  __shared__ V tr[BLOCK];                                       // 64 row sums per wave
+  const int wslot = (threadIdx.x / WAVE) * WAVE;
   const int wglobal = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
   const int wstride = gridDim.x * (BLOCK / WAVE);
   for (int wt = wglobal; wt < nwt; wt += wstride) {
@@ -505,16 +570,18 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csrw(State<Sc>* st, Sc* partial,
 #pragma unroll
     for (int p = 0; p < LPR; ++p)
       for (int q = beg[p] + sub + LPR; q < end[p]; q += LPR) ys[p] = axpy(ys[p], a.val[q], a.xin[a.ci[q]]);
-    // butterfly within each group of LPR lanes, then lane L takes row row0 + L
-    V y = zero<V>();
-    const int src = (lane % RPP) * LPR;
+    // row sums within each group of LPR lanes (DPP), then the group leaders put
+    // them in the wave's LDS slice in row order and lane L reads row row0 + L
 #pragma unroll
     for (int p = 0; p < LPR; ++p) {
-#pragma unroll
-      for (int m = LPR / 2; m > 0; m >>= 1) add_(ys[p], shfl_xor_(ys[p], m));
-      const V t = shfl_(ys[p], src);
-      if (lane / RPP == p) y = t;
+      ys[p] = group_sum<LPR>(ys[p]);
+      if (sub == 0) tr[wslot + p * RPP + grp] = ys[p];
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    V y = tr[wslot + lane];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     const int row = row0 + lane;
     if (row < a.nrows) {
       if constexpr (MODE == SM_PLAIN) {
