@@ -47,7 +47,7 @@ def measured_traffic(workload):
     import re
 
     path = os.path.join(ROOT, "profiles", f"spmv_step_{workload}.md")
-    src = os.path.join(ROOT, "paper_1106_3678_amd", "csrc", "mlb_kernels.hpp")
+    src = os.path.join(ROOT, "paper_1106_3678_amd", "csrc", "mlb_spmv.hpp")   # the SpMV kernels
     if not os.path.exists(path):
         return None
     text = open(path).read()

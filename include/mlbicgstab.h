@@ -157,8 +157,9 @@ const char* mlbicgstab_last_error(void);
  * for MLB_PREC_FP32_IR, the fp32) iteration on the solver's stream over the
  * workspace left by the last solve -- the same kernels in the same order as in
  * a solve, with the one-workgroup coefficient recurrences left out -- and
- * brackets every launch of the requested kernel class with a pair of HIP
- * events.  *ms_per_launch receives the mean bracketed duration.  Requires a
+ * attaches a HIP start/stop event pair to every launch of the requested kernel
+ * class (hipExtLaunchKernel: the events take that kernel's own start and end
+ * times).  *ms_per_launch receives the mean duration.  Requires a
  * prior solve() whose Q is still allocated (it is read again); scrambles the
  * library's workspace (not b, x or Q).
  */

@@ -9,6 +9,7 @@
 // stays at most two cycles ahead of the device, so the iteration never waits
 // for the host and the kernels of at most one cycle run after the end (they
 // return at once because the device flag is set).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +29,7 @@
 
 #include "../../include/mlbicgstab.h"
 #include "mlb_kernels.hpp"
+#include "mlb_spmv.hpp"
 #include "mlb_precond.hpp"
 #include "mlb_transpose.hpp"
 
@@ -168,6 +170,20 @@ static Mat<V> build_transpose(const Mat<V>& A, Allocs& al, hipStream_t s) {
 
 // ------------------------------------------------------------------ launch dispatch
 
+// Kernel timing hook: a pair of HIP events attached to one launch.  With
+// hipExtLaunchKernel the events take the kernel's own start and end times
+// (no separate marker packets on the stream).
+struct Timed {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+#define MLB_LAUNCH(kernel, grid, stream, tm, ...)                                                       \
+  do {                                                                                                 \
+    if ((tm).start)                                                                                    \
+      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, stream, (tm).start, (tm).stop, 0, __VA_ARGS__); \
+    else                                                                                               \
+      kernel<<<grid, BLOCK, 0, stream>>>(__VA_ARGS__);                                                 \
+  } while (0)
+
 static int bucket(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
 // Launches the SpMV kernel for A's format and lanes-per-row with epilogue MODE.
@@ -185,22 +201,22 @@ static int occupancy_of(K kernel) {
 
 template <class V, class Sc, int MODE, int ND>
 static int launch_spmv_nd(const Mat<V>& A, int grid, hipStream_t s, State<Sc>* st, Sc* part, const SpmvArgs<V>& a,
-                          int phase, int i, int j, int n, int flags) {
+                          int phase, int i, int j, int n, int flags, Timed tm = {}) {
 #define MLB_SPMV_CASE(L)                                                                                     \
   if (A.format == MLB_CSR) {                                                                                 \
     if (!grid) return occupancy_of(k_spmv<V, Sc, ND, L, 0, MODE>);                                          \
-    k_spmv<V, Sc, ND, L, 0, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);                \
+    MLB_LAUNCH((k_spmv<V, Sc, ND, L, 0, MODE>), grid, s, tm, st, part, a, phase, i, j, n, flags);            \
   } else {                                                                                                   \
     if (!grid) return occupancy_of(k_spmv<V, Sc, ND, L, 1, MODE>);                                          \
-    k_spmv<V, Sc, ND, L, 1, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);                \
+    MLB_LAUNCH((k_spmv<V, Sc, ND, L, 1, MODE>), grid, s, tm, st, part, a, phase, i, j, n, flags);            \
   }
 #define MLB_SPMV_WCASE(L)                                                                                    \
   if (A.format == MLB_CSR) {                                                                                 \
     if (!grid) return occupancy_of(k_spmv_csrw<V, Sc, ND, L, MODE>);                                        \
-    k_spmv_csrw<V, Sc, ND, L, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, flags);                             \
+    MLB_LAUNCH((k_spmv_csrw<V, Sc, ND, L, MODE>), grid, s, tm, st, part, a, flags);                         \
   } else {                                                                                                   \
     if (!grid) return occupancy_of(k_spmv<V, Sc, ND, L, 1, MODE>);                                          \
-    k_spmv<V, Sc, ND, L, 1, MODE><<<grid, BLOCK, 0, s>>>(st, part, a, phase, i, j, n, flags);                \
+    MLB_LAUNCH((k_spmv<V, Sc, ND, L, 1, MODE>), grid, s, tm, st, part, a, phase, i, j, n, flags);            \
   }
   switch (A.lpr) {
     case 4: MLB_SPMV_WCASE(4) break;
@@ -257,7 +273,8 @@ struct Engine {
   Mat<V> A, AH;
   V *G = nullptr, *W = nullptr, *F = nullptr, *r = nullptr, *gt = nullptr, *z = nullptr;
   State<Sc>* st = nullptr;
-  Sc* part = nullptr;
+  Sc* part = nullptr;    // per-workgroup partial sums of the last reducing pass
+  Sc* part2 = nullptr;   // their first-stage sums (long rows)
   int grid_vec = 1, grid_spmv = 1;
   hipStream_t s = nullptr;
   int* host_done = nullptr;       // pinned, mapped
@@ -301,6 +318,7 @@ struct Engine {
     grid_vec = grid_for(N, std::min(MAX_GRID, 8 * cus));
     grid_spmv = grid_for(A.nbrows, std::min(MAX_GRID, occ * cus));
     part = al.get<Sc>((size_t)std::max(grid_vec, grid_spmv) * (NMAX + 1));
+    part2 = al.get<Sc>((size_t)PSUM_GRID * (NMAX + 1));
     if (ext_flag) {
       host_done = ext_flag;
       own_flag = false;
@@ -320,46 +338,54 @@ struct Engine {
 
   static size_t bytes(int N, int n, long long grid) {
     return sizeof(V) * ((size_t)N * (2 * n + std::max(n - 1, 1) + 3)) + sizeof(State<Sc>) +
-           sizeof(Sc) * (size_t)grid * (NMAX + 1);
+           sizeof(Sc) * (size_t)(grid + PSUM_GRID) * (NMAX + 1);
   }
 
   // ---- single launches --------------------------------------------------
 
   bool launch_scalars = true;   // false while timing kernels (same kernel work, no recurrence)
   int force_flags = 0;          // OR-ed into every pass's flags (timing: F_IGNORE_DONE)
-  // Timing hook: HIP event pairs recorded around every launch of one kernel class.
+  // Timing hook: every launch of kernel class ev_kernel gets a start/stop event
+  // pair attached to the launch itself; the pairs are collected in ev_list.
   int ev_kernel = -1;
   std::vector<hipEvent_t>* ev_list = nullptr;
-  struct Bracket {
-    Engine& e;
-    bool on;
-    Bracket(Engine& e_, int kind) : e(e_), on(e_.ev_kernel == kind && e_.ev_list) {
-      if (on) record();
+  Timed timed(int kind) {
+    Timed tm;
+    if (ev_kernel != kind || !ev_list) return tm;
+    if (hipEventCreate(&tm.start) != hipSuccess) return Timed{};
+    if (hipEventCreate(&tm.stop) != hipSuccess) {
+      (void)hipEventDestroy(tm.start);
+      return Timed{};
     }
-    ~Bracket() {
-      if (on) record();
-    }
-    void record() {
-      hipEvent_t ev;
-      if (hipEventCreate(&ev) == hipSuccess) {
-        (void)hipEventRecord(ev, e.s);
-        e.ev_list->push_back(ev);
-      }
-    }
-  };
+    ev_list->push_back(tm.start);
+    ev_list->push_back(tm.stop);
+    return tm;
+  }
 
   // Sum the partials of the pass just launched and run the recurrence of `phase`.
+  // Rows longer than 64 bytes are first summed in PSUM_GRID contiguous shares
+  // (k_psum), so that the one-workgroup stage reads few rows.
+  static constexpr int PSUM_GRID = 64;
+  template <int STRIDE>
+  void scalar_t(int nblocks, int nsum, int phase, int i, int j) {
+    if (STRIDE * sizeof(Sc) > 64 && nblocks > PSUM_GRID) {
+      k_psum<Sc, STRIDE><<<PSUM_GRID, BLOCK, 0, s>>>(st, part, nblocks, nsum, part2);
+      k_scalar<Sc, STRIDE><<<1, BLOCK, 0, s>>>(st, part2, PSUM_GRID, nsum, phase, i, j, n);
+    } else {
+      k_scalar<Sc, STRIDE><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n);
+    }
+  }
   void scalar(int nblocks, int stride, int nsum, int phase, int i, int j) {
     if (!launch_scalars) return;
     switch (stride) {
-      case 4: k_scalar<Sc, 4><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
-      case 5: k_scalar<Sc, 5><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
-      case 8: k_scalar<Sc, 8><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
-      case 9: k_scalar<Sc, 9><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
-      case 16: k_scalar<Sc, 16><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
-      case 17: k_scalar<Sc, 17><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
-      case 32: k_scalar<Sc, 32><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
-      default: k_scalar<Sc, 33><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n); break;
+      case 4: scalar_t<4>(nblocks, nsum, phase, i, j); break;
+      case 5: scalar_t<5>(nblocks, nsum, phase, i, j); break;
+      case 8: scalar_t<8>(nblocks, nsum, phase, i, j); break;
+      case 9: scalar_t<9>(nblocks, nsum, phase, i, j); break;
+      case 16: scalar_t<16>(nblocks, nsum, phase, i, j); break;
+      case 17: scalar_t<17>(nblocks, nsum, phase, i, j); break;
+      case 32: scalar_t<32>(nblocks, nsum, phase, i, j); break;
+      default: scalar_t<33>(nblocks, nsum, phase, i, j); break;
     }
   }
 
@@ -397,12 +423,12 @@ struct Engine {
     a.xin = gin; a.out1 = W + (size_t)i * N; a.out2 = gin == Gi ? nullptr : Gi;
     a.Q = Q; a.ldq = ldq; a.d0 = i; a.nd = n - i;
     flags |= force_flags;
-    Bracket br(*this, MLB_KERNEL_SPMV_STEP);
+    const Timed tm = timed(MLB_KERNEL_SPMV_STEP);
     switch (nb) {
-      case 4: launch_spmv_nd<V, Sc, SM_STEP, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
-      case 8: launch_spmv_nd<V, Sc, SM_STEP, 8>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
-      case 16: launch_spmv_nd<V, Sc, SM_STEP, 16>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
-      default: launch_spmv_nd<V, Sc, SM_STEP, 32>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags); break;
+      case 4: launch_spmv_nd<V, Sc, SM_STEP, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
+      case 8: launch_spmv_nd<V, Sc, SM_STEP, 8>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
+      case 16: launch_spmv_nd<V, Sc, SM_STEP, 16>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
+      default: launch_spmv_nd<V, Sc, SM_STEP, 32>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
     }
     if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, std::max(nb, 3), n - i, PH_SPMV_STEP, i, 0);
   }
@@ -410,9 +436,9 @@ struct Engine {
     const V* gh = G + (size_t)i_prev * N;
     const V* w = W + (size_t)i_prev * N;
     flags |= force_flags;
-    Bracket br(*this, MLB_KERNEL_ALPHA_STEP);
+    const Timed tm = timed(MLB_KERNEL_ALPHA_STEP);
 #define MLB_ALPHA(B) \
-  k_alpha<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, gh, r, w, Q, ldq, d0, nd, xrec, K, phase, i, j, n, flags)
+  MLB_LAUNCH((k_alpha<V, Sc, B>), grid_vec, s, tm, st, part, N, x, gh, r, w, Q, ldq, d0, nd, xrec, K, phase, i, j, n, flags)
     switch (nb) {
       case 4: MLB_ALPHA(4); break;
       case 8: MLB_ALPHA(8); break;
@@ -424,10 +450,10 @@ struct Engine {
   }
   void combine(int t0, int t1, int nf, int i, int j, int flags = 0) {
     flags |= force_flags;
-    Bracket br(*this, MLB_KERNEL_COMBINE);
+    const Timed tm = timed(MLB_KERNEL_COMBINE);
 #define MLB_COMB(B)                                                                                            \
-  k_combine<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, r, W, G, N, t0, t1, gt, F, N, nf, PH_COMBINE, i, j, n, \
-                                                 flags)
+  MLB_LAUNCH((k_combine<V, Sc, B>), grid_vec, s, tm, st, part, N, (const V*)r, (const V*)W, (const V*)G, (long long)N, \
+             t0, t1, gt, (const V*)F, (long long)N, nf, (int)PH_COMBINE, i, j, n, flags)
     switch (nb) {
       case 4: MLB_COMB(4); break;
       case 8: MLB_COMB(8); break;
@@ -824,7 +850,7 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
 // Mean duration of one kernel class as it runs inside the iteration: whole cycles
 // are replayed (same kernels, same predecessors, same cache context; the one-
 // workgroup recurrences are left out and the done flag is ignored) and only the
-// requested kernel's launches are bracketed by HIP event pairs.
+// requested kernel's launches carry a HIP start/stop event pair.
 template <class V>
 static double time_kernel_impl(Engine<V>& e, int kernel, int reps) {
   Allocs tmp(e.s, false);

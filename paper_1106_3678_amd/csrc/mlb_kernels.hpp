@@ -65,7 +65,6 @@ struct State {
   double bnrm2, err, uu;
   Sc e, alpha, omega;
   Sc c[NMAX];
-  Sc S[NMAX * NMAX];    // S[s * NMAX + u] = q_s^H w_u  (s >= u)
   Sc t[NMAX];           // pending beta~ coefficients (of the w columns)
   Sc tg[NMAX];          // -t / omega (of the g columns)
   Sc beta[NMAX];        // pending beta coefficients
@@ -74,6 +73,7 @@ struct State {
   long long best_k;     // iteration at which best_err last halved
   long long stag_window;  // > 0: stop with flag 2 after this many iterations without halving
   int* host_done;       // host-mapped copy of `done` (may be null)
+  Sc S[NMAX * NMAX];    // S[s * NMAX + u] = q_s^H w_u  (s >= u); last, so rows s >= n can be left out of copies
 };
 
 // ---------------------------------------------------------------- reductions
@@ -94,37 +94,6 @@ __device__ inline void add_(double& a, double b) { a += b; }
 __device__ inline void add_(float& a, float b) { a += b; }
 template <class R>
 __device__ inline void add_(cplx<R>& a, cplx<R> b) { a.re += b.re; a.im += b.im; }
-
-// Sum over aligned groups of G = 4 or 8 lanes with DPP moves (VALU only):
-// quad permutes for lane ^ 1 and lane ^ 2, then the half-row mirror (lane i
-// of an 8-lane half-row takes lane 7 - i, which lies in the other quad).
-// Every lane of the group ends with the group's sum, added in a fixed order.
-template <int CTRL>
-__device__ inline float dpp_(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ inline double dpp_(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL, class R>
-__device__ inline cplx<R> dpp_(cplx<R> v) {
-  return {dpp_<CTRL>(v.re), dpp_<CTRL>(v.im)};
-}
-constexpr int DPP_XOR1 = 0xB1;       // quad_perm [1, 0, 3, 2]
-constexpr int DPP_XOR2 = 0x4E;       // quad_perm [2, 3, 0, 1]
-constexpr int DPP_HALF_MIRROR = 0x141;
-
-template <int G, class T>
-__device__ inline T group_sum(T v) {
-  static_assert(G == 4 || G == 8, "DPP group sums cover 4 or 8 lanes");
-  add_(v, dpp_<DPP_XOR1>(v));
-  add_(v, dpp_<DPP_XOR2>(v));
-  if constexpr (G == 8) add_(v, dpp_<DPP_HALF_MIRROR>(v));
-  return v;
-}
 
 template <class T>
 __device__ inline T wave_sum(T v) {
@@ -285,57 +254,53 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
   }
 }
 
-// One workgroup: sum the partials of the previous pass in a fixed order
-// (lane-strided over workgroups, then a tree; the order depends only on the
-// producer's grid size) and run the coefficient recurrence on one lane.
-// STRIDE is the producer's partial row length; all loads are issued before
-// any reduction.
+// Sums rows [r0, r1) of a pass's partials (row length STRIDE; at most
+// MAX_PARTIAL_ROWS rows) into sums[0..nsum) in LDS, in a fixed order: lane-
+// strided over the rows, then a tree over lanes and a fixed sweep over waves.
+// All loads of a lane are issued before any is added where the registers allow
+// (a compile-time trip count).  Ends with a barrier; every thread must call it.
 template <class Sc, int STRIDE>
-__global__ __launch_bounds__(BLOCK) void k_scalar(State<Sc>* st, const Sc* __restrict__ partial, int nblocks,
-                                                  int nsum, int phase, int i, int j, int n) {
-  if (st->done) return;
+__device__ void sum_rows(const Sc* __restrict__ partial, int r0, int r1, int nsum, Sc* sums) {
   __shared__ Sc red2[BLOCK / WAVE][STRIDE];
-  __shared__ Sc sums[STRIDE];
   const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  const int nrows = r1 - r0;
   Sc acc[STRIDE];
 #pragma unroll
   for (int d = 0; d < STRIDE; ++d) acc[d] = zero<Sc>();
-  // up to MAX_PARTIAL_ROWS producer workgroups: a fixed trip count lets every
-  // load of a lane be in flight at once (the order of the sums stays fixed)
-  constexpr int KR = MAX_PARTIAL_ROWS / BLOCK;                  // rows per lane
-  // rows loaded together: as many as fit in a budget of 64 eight-byte registers per lane
+  constexpr int KR = MAX_PARTIAL_ROWS / BLOCK;                  // rows per lane at most
   constexpr int WORDS = (int)(STRIDE * sizeof(Sc) / 8);
-  constexpr int KC = WORDS <= 8 ? KR : WORDS <= 16 ? 4 : 2;
   if constexpr (WORDS > 32) {
-    // long rows (complex, large n): the accumulators alone take half the
-    // register file, so each row is summed as it arrives
-    for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
-      const Sc* row = partial + (size_t)b * STRIDE;
+    // long rows: the accumulators alone take half the register file, so each
+    // row is summed as it arrives
+    for (int b = threadIdx.x; b < nrows; b += BLOCK) {
+      const Sc* row = partial + (size_t)(r0 + b) * STRIDE;
 #pragma unroll
       for (int d = 0; d < STRIDE; ++d)
         if (d < nsum) add_(acc[d], row[d]);
     }
   } else {
+    constexpr int KC = WORDS <= 8 ? KR : WORDS <= 16 ? 2 : 1;   // rows loaded together
 #pragma unroll
-  for (int k0 = 0; k0 < KR; k0 += KC) {
-    Sc v[KC][STRIDE];
+    for (int k0 = 0; k0 < KR; k0 += KC) {
+      if (k0 * BLOCK >= nrows) break;   // uniform
+      Sc v[KC][STRIDE];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const int b = threadIdx.x + (k0 + k) * BLOCK;
-      // rows past nblocks re-read row 0 and entries past nsum are read unused:
-      // the buffer holds STRIDE entries for every producer workgroup
-      const Sc* row = partial + (size_t)(b < nblocks ? b : 0) * STRIDE;
+      for (int k = 0; k < KC; ++k) {
+        const int b = threadIdx.x + (k0 + k) * BLOCK;
+        // rows past the range re-read its first row and entries past nsum are
+        // read unused: the buffer holds STRIDE entries for every row
+        const Sc* row = partial + (size_t)(r0 + (b < nrows ? b : 0)) * STRIDE;
 #pragma unroll
-      for (int d = 0; d < STRIDE; ++d) v[k][d] = row[d];
+        for (int d = 0; d < STRIDE; ++d) v[k][d] = row[d];
+      }
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const bool on = threadIdx.x + (k0 + k) * BLOCK < nrows;
+#pragma unroll
+        for (int d = 0; d < STRIDE; ++d)
+          if (on && d < nsum) add_(acc[d], v[k][d]);
+      }
     }
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const bool on = threadIdx.x + (k0 + k) * BLOCK < nblocks;
-#pragma unroll
-      for (int d = 0; d < STRIDE; ++d)
-        if (on && d < nsum) add_(acc[d], v[k][d]);
-    }
-  }
   }
 #pragma unroll
   for (int d = 0; d < STRIDE; ++d) {
@@ -351,264 +316,42 @@ __global__ __launch_bounds__(BLOCK) void k_scalar(State<Sc>* st, const Sc* __res
     sums[threadIdx.x] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) scalar_program(st, sums, phase, i, j, n);
 }
 
-// ---------------------------------------------------------------- SpMV tiles
-// A workgroup computes y = A x for a tile of rows into LDS: each wave takes
-// 64 (block) rows, LPR lanes per row, so the column/value streams of one row
-// are read by adjacent lanes (coalesced) and the row sums are reduced with
-// butterfly shuffles.  The epilogue then runs one lane per row.
-
-template <class V, int LPR>
-__device__ inline void csr_tile(const int* __restrict__ rp, const int* __restrict__ ci, const V* __restrict__ val,
-                                const V* __restrict__ xin, int nrows, int row0, V* ylds) {
-  const int lane = threadIdx.x % WAVE;
-  const int wbase = (threadIdx.x / WAVE) * WAVE;
-  constexpr int RPP = WAVE / LPR;
-  const int sub = lane % LPR, grp = lane / LPR;
-  if constexpr (LPR <= 8) {
-    // All LPR passes at once: row bounds, then one entry per lane and pass,
-    // then the gathers, so every load of a stage is in flight together.
-    int beg[LPR], end[LPR];
-#pragma unroll
-    for (int p = 0; p < LPR; ++p) {
-      const int row = row0 + wbase + p * RPP + grp;
-      beg[p] = row < nrows ? rp[row] : 0;
-      end[p] = row < nrows ? rp[row + 1] : 0;
-    }
-    V acc[LPR];
-    int col[LPR];
-    V v[LPR];
-#pragma unroll
-    for (int p = 0; p < LPR; ++p) {
-      const int q = beg[p] + sub;
-      const bool on = q < end[p];
-      col[p] = on ? ci[q] : 0;
-      v[p] = on ? val[q] : zero<V>();
-    }
-#pragma unroll
-    for (int p = 0; p < LPR; ++p) acc[p] = axpy(zero<V>(), v[p], xin[col[p]]);
-    // rows longer than LPR entries
-#pragma unroll
-    for (int p = 0; p < LPR; ++p)
-      for (int q = beg[p] + sub + LPR; q < end[p]; q += LPR) acc[p] = axpy(acc[p], val[q], xin[ci[q]]);
-#pragma unroll
-    for (int p = 0; p < LPR; ++p) {
-#pragma unroll
-      for (int m = LPR / 2; m > 0; m >>= 1) add_(acc[p], shfl_xor_(acc[p], m));
-      if (sub == 0) ylds[wbase + p * RPP + grp] = acc[p];
-    }
-  } else {
-#pragma unroll 2
-    for (int p = 0; p < LPR; ++p) {
-      const int lr = wbase + p * RPP + grp;
-      const int row = row0 + lr;
-      V acc = zero<V>();
-      if (row < nrows) {
-        const int beg = rp[row], end = rp[row + 1];
-        for (int q = beg + sub; q < end; q += LPR) acc = axpy(acc, val[q], xin[ci[q]]);
-      }
-#pragma unroll
-      for (int m = LPR / 2; m > 0; m >>= 1) add_(acc, shfl_xor_(acc, m));
-      if (sub == 0) ylds[lr] = acc;
-    }
-  }
+// First stage for long partial rows (many shadow vectors, complex): workgroup
+// g sums the g-th contiguous share of the rows into row g of `out`, so that
+// the one-workgroup stage reads gridDim.x rows instead of nblocks.
+template <class Sc, int STRIDE>
+__global__ __launch_bounds__(BLOCK) void k_psum(const State<Sc>* st, const Sc* __restrict__ partial, int nblocks,
+                                                int nsum, Sc* __restrict__ out) {
+  if (st->done) return;
+  __shared__ Sc sums[STRIDE];
+  const int r0 = (int)((long long)nblocks * blockIdx.x / gridDim.x);
+  const int r1 = (int)((long long)nblocks * (blockIdx.x + 1) / gridDim.x);
+  sum_rows<Sc, STRIDE>(partial, r0, r1, nsum, sums);
+  if (threadIdx.x < nsum) out[(size_t)blockIdx.x * STRIDE + threadIdx.x] = sums[threadIdx.x];
 }
 
-template <class V, int LPR>
-__device__ inline void bsr3_tile(const int* __restrict__ rp, const int* __restrict__ ci, const V* __restrict__ val,
-                                 const V* __restrict__ xin, int nbrows, int brow0, V* ylds) {
-  const int lane = threadIdx.x % WAVE;
-  const int wbase = (threadIdx.x / WAVE) * WAVE;
-  constexpr int RPP = WAVE / LPR;
-  const int sub = lane % LPR, grp = lane / LPR;
-#pragma unroll 2
-  for (int p = 0; p < LPR; ++p) {
-    const int lb = wbase + p * RPP + grp;
-    const int brow = brow0 + lb;
-    V a0 = zero<V>(), a1 = zero<V>(), a2 = zero<V>();
-    if (brow < nbrows) {
-      const int beg = rp[brow], end = rp[brow + 1];
-      for (int q = beg + sub; q < end; q += LPR) {
-        const V* blk = val + (size_t)9 * q;
-        const int c3 = 3 * ci[q];
-        const V x0 = xin[c3], x1 = xin[c3 + 1], x2 = xin[c3 + 2];
-        a0 = axpy(axpy(axpy(a0, blk[0], x0), blk[1], x1), blk[2], x2);
-        a1 = axpy(axpy(axpy(a1, blk[3], x0), blk[4], x1), blk[5], x2);
-        a2 = axpy(axpy(axpy(a2, blk[6], x0), blk[7], x1), blk[8], x2);
-      }
-    }
-#pragma unroll
-    for (int m = LPR / 2; m > 0; m >>= 1) {
-      add_(a0, shfl_xor_(a0, m));
-      add_(a1, shfl_xor_(a1, m));
-      add_(a2, shfl_xor_(a2, m));
-    }
-    if (sub == 0) {
-      ylds[3 * lb] = a0;
-      ylds[3 * lb + 1] = a1;
-      ylds[3 * lb + 2] = a2;
-    }
-  }
-}
-
-// SpMV epilogue modes
-enum SpmvMode : int {
-  SM_PLAIN = 0,   // out1 = A x
-  SM_RESID = 1,   // out1 = b - A x ; sums: ||out1||^2, ||b||^2, q_1^H out1
-  SM_STEP = 2,    // out1 = A x ; out2 = x (if given) ; sums: q_s^H out1, s in [d0, d0+nd)
-  SM_OMEGA = 3    // out1 = A x ; sums: out1^H out1, out1^H x
-};
-
-template <class V>
-struct SpmvArgs {
-  int format;                 // 0 CSR, 1 BSR3
-  int nrows;                  // scalar rows
-  int nbrows;                 // block rows (BSR3) or rows (CSR)
-  const int* rp;
-  const int* ci;
-  const V* val;
-  const V* xin;
-  V* out1;
-  V* out2;
-  const V* b;                 // SM_RESID
-  const V* Q;                 // dots against Q columns [d0, d0+nd)
-  long long ldq;
-  int d0, nd;
-};
-
-template <class V, class Sc, int ND, int LPR, int FMT, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_spmv(State<Sc>* st, Sc* partial, SpmvArgs<V> a, int phase, int i, int j,
-                                                int n, int flags) {
-  if (!(flags & F_IGNORE_DONE) && st->done) return;
-  constexpr int TROWS = FMT == 0 ? BLOCK : 3 * BLOCK;   // scalar rows per tile
-  constexpr int NA = ND > 3 ? ND : 3;
-  __shared__ V ylds[TROWS];
-  V acc[NA];
-#pragma unroll
-  for (int d = 0; d < NA; ++d) acc[d] = zero<V>();
-  const int ntiles = (a.nbrows + BLOCK - 1) / BLOCK;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    if constexpr (FMT == 0) csr_tile<V, LPR>(a.rp, a.ci, a.val, a.xin, a.nbrows, tile * BLOCK, ylds);
-    else bsr3_tile<V, LPR>(a.rp, a.ci, a.val, a.xin, a.nbrows, tile * BLOCK, ylds);
-    __syncthreads();
-    const int rbase = tile * TROWS;
-    for (int e = threadIdx.x; e < TROWS; e += BLOCK) {
-      const int row = rbase + e;
-      if (row >= a.nrows) break;
-      V y = ylds[e];
-      if constexpr (MODE == SM_PLAIN) {
-        a.out1[row] = y;
-      } else if constexpr (MODE == SM_RESID) {
-        V bv = a.b[row];
-        V rv = bv - y;
-        a.out1[row] = rv;
-        cdot_acc(acc[0], rv, rv);
-        cdot_acc(acc[1], bv, bv);
-        if (a.nd > 0) cdot_acc(acc[2], a.Q[row], rv);
-      } else if constexpr (MODE == SM_STEP) {
-        a.out1[row] = y;
-        if (a.out2) a.out2[row] = a.xin[row];
-#pragma unroll
-        for (int d = 0; d < ND; ++d)
-          if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
-      } else {  // SM_OMEGA
-        a.out1[row] = y;
-        cdot_acc(acc[0], y, y);
-        cdot_acc(acc[1], y, a.xin[row]);
-      }
-    }
-    __syncthreads();
-  }
-  if (MODE == SM_PLAIN || (flags & F_SKIP_SCALAR)) return;
-  const int nsum = MODE == SM_RESID ? 3 : (MODE == SM_OMEGA ? 2 : a.nd);
-  block_partials<NA>(acc, nsum, partial);
-}
-
-// CSR SpMV with LPR <= 8 lanes per row, wave-local: each wave computes 64
-// consecutive rows (LPR passes of 64/LPR rows, all loads of a stage issued
-// together), moves each row sum to lane "row - first row" with shuffles and
-// runs the epilogue one lane per row.  No LDS tile and no workgroup barrier
-// inside the row loop, so waves stream independently.
-template <class V, class Sc, int ND, int LPR, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_spmv_csrw(State<Sc>* st, Sc* partial, SpmvArgs<V> a, int flags) {
-  if (!(flags & F_IGNORE_DONE) && st->done) return;
-  constexpr int NA = ND > 3 ? ND : 3;
-  constexpr int RPP = WAVE / LPR;
-  V acc[NA];
-#pragma unroll
-  for (int d = 0; d < NA; ++d) acc[d] = zero<V>();
-  const int lane = threadIdx.x % WAVE;
-  const int sub = lane % LPR, grp = lane / LPR;
-  const int nwt = (a.nrows + WAVE - 1) / WAVE;                 // wave tiles
-  __shared__ V tr[BLOCK];                                       // 64 row sums per wave
-  const int wslot = (threadIdx.x / WAVE) * WAVE;
-  const int wglobal = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
-  const int wstride = gridDim.x * (BLOCK / WAVE);
-  for (int wt = wglobal; wt < nwt; wt += wstride) {
-    const int row0 = wt * WAVE;
-    int beg[LPR], end[LPR];
-#pragma unroll
-    for (int p = 0; p < LPR; ++p) {
-      const int row = row0 + p * RPP + grp;
-      beg[p] = row < a.nrows ? a.rp[row] : 0;
-      end[p] = row < a.nrows ? a.rp[row + 1] : 0;
-    }
-    int col[LPR];
-    V v[LPR];
-#pragma unroll
-    for (int p = 0; p < LPR; ++p) {
-      const int q = beg[p] + sub;
-      const bool on = q < end[p];
-      col[p] = on ? a.ci[q] : 0;
-      v[p] = on ? a.val[q] : zero<V>();
-    }
-    V ys[LPR];
-#pragma unroll
-    for (int p = 0; p < LPR; ++p) ys[p] = axpy(zero<V>(), v[p], a.xin[col[p]]);
-#pragma unroll
-    for (int p = 0; p < LPR; ++p)
-      for (int q = beg[p] + sub + LPR; q < end[p]; q += LPR) ys[p] = axpy(ys[p], a.val[q], a.xin[a.ci[q]]);
-    // row sums within each group of LPR lanes (DPP), then the group leaders put
-    // them in the wave's LDS slice in row order and lane L reads row row0 + L
-#pragma unroll
-    for (int p = 0; p < LPR; ++p) {
-      ys[p] = group_sum<LPR>(ys[p]);
-      if (sub == 0) tr[wslot + p * RPP + grp] = ys[p];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    V y = tr[wslot + lane];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const int row = row0 + lane;
-    if (row < a.nrows) {
-      if constexpr (MODE == SM_PLAIN) {
-        a.out1[row] = y;
-      } else if constexpr (MODE == SM_RESID) {
-        V bv = a.b[row];
-        V rv = bv - y;
-        a.out1[row] = rv;
-        cdot_acc(acc[0], rv, rv);
-        cdot_acc(acc[1], bv, bv);
-        if (a.nd > 0) cdot_acc(acc[2], a.Q[row], rv);
-      } else if constexpr (MODE == SM_STEP) {
-        a.out1[row] = y;
-        if (a.out2) a.out2[row] = a.xin[row];
-#pragma unroll
-        for (int d = 0; d < ND; ++d)
-          if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
-      } else {  // SM_OMEGA
-        a.out1[row] = y;
-        cdot_acc(acc[0], y, y);
-        cdot_acc(acc[1], y, a.xin[row]);
-      }
-    }
-  }
-  if (MODE == SM_PLAIN || (flags & F_SKIP_SCALAR)) return;
-  const int nsum = MODE == SM_RESID ? 3 : (MODE == SM_OMEGA ? 2 : a.nd);
-  block_partials<NA>(acc, nsum, partial);
+// One workgroup: sum the partials of the previous pass (or of k_psum) in a
+// fixed order and run the coefficient recurrence on one lane.  The state is
+// staged in LDS for the recurrence (its loops read the n x n Gram matrix and
+// the coefficient lists entry by entry) and written back afterwards; rows
+// s >= n of the Gram matrix are never touched and stay out of both copies.
+template <class Sc, int STRIDE>
+__global__ __launch_bounds__(BLOCK) void k_scalar(State<Sc>* st, const Sc* __restrict__ partial, int nblocks,
+                                                  int nsum, int phase, int i, int j, int n) {
+  if (st->done) return;
+  static_assert(sizeof(State<Sc>) % 8 == 0 && offsetof(State<Sc>, S) % 8 == 0, "state is copied in 8-byte words");
+  __shared__ State<Sc> ss;
+  __shared__ Sc sums[STRIDE];
+  const int nwords = (int)((offsetof(State<Sc>, S) + sizeof(Sc) * (size_t)n * NMAX) / 8);
+  unsigned long long* gw = reinterpret_cast<unsigned long long*>(st);
+  unsigned long long* lw = reinterpret_cast<unsigned long long*>(&ss);
+  for (int w = threadIdx.x; w < nwords; w += BLOCK) lw[w] = gw[w];
+  sum_rows<Sc, STRIDE>(partial, 0, nblocks, nsum, sums);   // its barriers also order the copy
+  if (threadIdx.x == 0) scalar_program(&ss, sums, phase, i, j, n);
+  __syncthreads();
+  for (int w = threadIdx.x; w < nwords; w += BLOCK) gw[w] = lw[w];
 }
 
 // ---------------------------------------------------------------- vector passes
@@ -663,7 +406,23 @@ __global__ __launch_bounds__(BLOCK) void k_combine(State<Sc>* st, Sc* partial, i
   __syncthreads();
   for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
     V g = r[row];
-    for (int s = t0; s < t1; ++s) {
+    // columns in groups of 4, all loads of a group issued before its updates
+    // (the order of the updates is unchanged)
+    int s = t0;
+    for (; s + 4 <= t1; s += 4) {
+      V wv[4], gv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        wv[u] = Wb[row + (s + u) * ldw];
+        gv[u] = Gb[row + (s + u) * ldw];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        g = axpy(g, tw[s + u], wv[u]);
+        g = axpy(g, tgv[s + u], gv[u]);
+      }
+    }
+    for (; s < t1; ++s) {
       g = axpy(g, tw[s], Wb[row + s * ldw]);
       g = axpy(g, tgv[s], Gb[row + s * ldw]);
     }
@@ -687,7 +446,15 @@ __global__ __launch_bounds__(BLOCK) void k_gcomb(const State<Sc>* st, int N, con
   __syncthreads();
   for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
     V v = g[row];
-    for (int s = 0; s < nb; ++s) v = axpy(v, bco[s], Gb[row + s * ldg]);
+    int s = 0;
+    for (; s + 4 <= nb; s += 4) {   // loads of 4 columns issued together, same order of updates
+      V gv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) gv[u] = Gb[row + (s + u) * ldg];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v = axpy(v, bco[s + u], gv[u]);
+    }
+    for (; s < nb; ++s) v = axpy(v, bco[s], Gb[row + s * ldg]);
     gout[row] = v;
   }
 }
