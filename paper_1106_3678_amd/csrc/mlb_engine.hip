@@ -254,7 +254,7 @@ __global__ void k_init_state(State<Sc>* st, double tol, long long maxit, double 
   st->uu = 0.0;
   st->e = st->alpha = zero<Sc>();
   st->omega = from_real<Sc>(1.0);
-  for (int q = 0; q < NMAX; ++q) st->c[q] = st->t[q] = st->tg[q] = st->beta[q] = zero<Sc>();
+  for (int q = 0; q < NMAX; ++q) st->c[q] = st->cinv[q] = st->t[q] = st->tg[q] = st->beta[q] = zero<Sc>();
   for (int q = 0; q < NMAX * NMAX; ++q) st->S[q] = zero<Sc>();
   for (int q = 0; q < 8; ++q) st->aux[q] = zero<Sc>();
   st->host_done = host_done;
@@ -365,10 +365,9 @@ struct Engine {
   // Sum the partials of the pass just launched and run the recurrence of `phase`.
   // Rows longer than 64 bytes are first summed in PSUM_GRID contiguous shares
   // (k_psum), so that the one-workgroup stage reads few rows.
-  static constexpr int PSUM_GRID = 64;
   template <int STRIDE>
   void scalar_t(int nblocks, int nsum, int phase, int i, int j) {
-    if (STRIDE * sizeof(Sc) > 64 && nblocks > PSUM_GRID) {
+    if (two_stage<Sc, STRIDE>() && nblocks > PSUM_GRID) {
       k_psum<Sc, STRIDE><<<PSUM_GRID, BLOCK, 0, s>>>(st, part, nblocks, nsum, part2);
       k_scalar<Sc, STRIDE><<<1, BLOCK, 0, s>>>(st, part2, PSUM_GRID, nsum, phase, i, j, n);
     } else {

@@ -6,7 +6,7 @@
 // N x n blocks, one row per lane), and reduces the inner products the next
 // scalar step needs into per-workgroup partials; a one-workgroup launch
 // (k_scalar) then sums the partials in a fixed order and runs the
-// coefficient recurrence on one lane.  Scalars never leave the device, and a
+// coefficient recurrence on one wave.  Scalars never leave the device, and a
 // device "done" flag makes every later pass return at once.
 //
 // The sequential beta~ and beta recurrences of the algorithm (each
@@ -34,6 +34,7 @@ namespace mlb {
 
 constexpr int NMAX = 32;        // largest n
 constexpr int MAX_PARTIAL_ROWS = 2048;   // most workgroups of a reducing pass
+constexpr int PSUM_GRID = 64;            // first-stage workgroups for long partial rows
 constexpr int BLOCK = 256;      // threads per workgroup (4 waves of 64)
 constexpr int WAVE = 64;
 
@@ -54,7 +55,7 @@ enum Phase : int {
 };
 
 // Everything the recurrences need, resident in device memory.  Written only
-// by k_scalar (one lane) and read by every later pass.
+// by k_scalar and read by every later pass.
 template <class Sc>
 struct State {
   int done;             // 1 once the solve has ended
@@ -65,6 +66,7 @@ struct State {
   double bnrm2, err, uu;
   Sc e, alpha, omega;
   Sc c[NMAX];
+  Sc cinv[NMAX];        // 1 / c
   Sc t[NMAX];           // pending beta~ coefficients (of the w columns)
   Sc tg[NMAX];          // -t / omega (of the g columns)
   Sc beta[NMAX];        // pending beta coefficients
@@ -126,10 +128,14 @@ __device__ void block_partials(V (&acc)[ND], int nd, Sc* __restrict__ partial) {
 }
 
 // ---------------------------------------------------------------- scalar program
-// Runs on one lane of the last workgroup.  Names follow Algorithm 7.1.
+// Runs on the 64 lanes of one wave of k_scalar, over the state staged in LDS.
+// Every lane evaluates the scalar bookkeeping (the same arithmetic on the same
+// values, so all lanes take the same branches) and lane 0 stores it; the two
+// triangular recurrences run across the lanes.  Names follow Algorithm 7.1.
 
 template <class Sc>
 __device__ inline void finish(State<Sc>* st, int flag) {
+  if (threadIdx.x % WAVE != 0) return;
   st->flag = flag;
   st->done = 1;
   if (st->host_done) *(volatile int*)st->host_done = 1;
@@ -140,17 +146,47 @@ __device__ inline Sc sc_div(Sc a, Sc b) { return a / b; }
 template <>
 __device__ inline double sc_div<double>(double a, double b) { return a / b; }
 
+// value of lane `src` (wave-uniform) in every lane
+__device__ inline double bcast_(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+template <class R>
+__device__ inline cplx<R> bcast_(cplx<R> v, int src) {
+  return {bcast_(v.re, src), bcast_(v.im, src)};
+}
+
+// Forward substitution x_s = -(d_s + sum_{lo<=u<s} x_u S[s][u]) / c_s for
+// s = lo..hi-1 (hi - lo <= 32), by columns: lane s - lo keeps the running sum
+// of row s, and at step u the lane of row u finishes x_u = -sum * (1/c_u),
+// which is broadcast to the rows below.  Each row adds its terms in the order
+// u = lo, lo+1, ..., as the sequential recurrence does.  Returns x_s in lane
+// s - lo (zero in the other lanes).
+template <class Sc>
+__device__ inline Sc forward_subst(const State<Sc>* st, const Sc* d, int lo, int hi) {
+  const int lane = threadIdx.x % WAVE;
+  const int s = lo + lane;
+  const bool mine = s < hi;
+  Sc acc = mine ? d[lane] : zero<Sc>();
+  Sc xs = zero<Sc>();
+  for (int u = lo; u < hi; ++u) {
+    const Sc xu = bcast_(zero<Sc>() - acc * st->cinv[u], u - lo);
+    if (s == u) xs = xu;
+    if (mine && s > u) acc = acc + xu * st->S[s * NMAX + u];
+  }
+  return xs;
+}
+
 // beta~ coefficients of step i (columns i..n-1) from d_s = q_s^H r (s = i..n-1):
 // t_s = -(d_s + sum_{u=i}^{s-1} t_u S[s][u]) / c_s ; tg_s = -t_s / omega.
 template <class Sc>
 __device__ inline void beta_tilde(State<Sc>* st, const Sc* d, int i, int n) {
-  const Sc om = st->omega;
-  for (int s = i; s < n; ++s) {
-    Sc acc = d[s - i];
-    for (int u = i; u < s; ++u) acc = acc + st->t[u] * st->S[s * NMAX + u];
-    Sc ts = zero<Sc>() - sc_div(acc, st->c[s]);
+  const Sc ts = forward_subst(st, d, i, n);
+  const int s = i + threadIdx.x % WAVE;
+  if (s < n) {
     st->t[s] = ts;
-    st->tg[s] = zero<Sc>() - sc_div(ts, om);
+    st->tg[s] = zero<Sc>() - sc_div(ts, st->omega);
   }
 }
 
@@ -160,8 +196,10 @@ template <class Sc>
 __device__ inline bool stagnated(State<Sc>* st, double err, long long k) {
   if (st->stag_window <= 0) return false;
   if (err < 0.5 * st->best_err) {
-    st->best_err = err;
-    st->best_k = k;
+    if (threadIdx.x % WAVE == 0) {
+      st->best_err = err;
+      st->best_k = k;
+    }
     return false;
   }
   return k - st->best_k >= st->stag_window;
@@ -169,60 +207,74 @@ __device__ inline bool stagnated(State<Sc>* st, double err, long long k) {
 
 template <class Sc>
 __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, int j, int n) {
+  const bool w0 = threadIdx.x % WAVE == 0;   // the lane that stores scalars
   switch (phase) {
     case PH_NONE:   // residual sums: ||r||^2, ||b||^2, q^H r
-      for (int d = 0; d < 3; ++d) st->aux[d] = sums[d];
+      if (w0)
+        for (int d = 0; d < 3; ++d) st->aux[d] = sums[d];
       break;
     case PH_SETUP: {
       double bn = sqrt(re(sums[1]));
       if (bn == 0.0) bn = 1.0;
-      st->bnrm2 = bn;
       double err = sqrt(re(sums[0])) / bn;
-      st->err = err;
-      st->best_err = err;
-      st->best_k = 0;
-      st->iter = 0;
-      st->e = sums[2];
+      if (w0) {
+        st->bnrm2 = bn;
+        st->err = err;
+        st->best_err = err;
+        st->best_k = 0;
+        st->iter = 0;
+        st->e = sums[2];
+      }
       if (!finite(err)) finish(st, -1);
       else if (err < st->tol) finish(st, 0);
       break;
     }
     case PH_INNER: {
-      long long k = ++st->iter;
+      const long long k = st->iter + 1;
       double err = sqrt(re(sums[0])) / st->bnrm2;
-      st->err = err;
+      if (w0) {
+        st->iter = k;
+        st->err = err;
+      }
       if (!finite(err)) { finish(st, -1); break; }
       if (err < st->tol) { finish(st, 0); break; }
       if (k >= st->maxit) { finish(st, 1); break; }
       if (stagnated(st, err, k)) { finish(st, 2); break; }
-      st->e = sums[1];                       // e = q_{i+1}^H r
+      if (w0) st->e = sums[1];               // e = q_{i+1}^H r
       if (j >= 1) beta_tilde(st, sums + 1, i, n);
       break;
     }
     case PH_HALF: {
       double uu = re(sums[0]);
       double err = sqrt(uu) / st->bnrm2;
-      st->uu = uu;
-      st->err = err;
+      if (w0) {
+        st->uu = uu;
+        st->err = err;
+      }
       if (!finite(err)) { finish(st, -1); break; }
-      if (err < st->tol) { st->iter += 1; finish(st, 0); }
+      if (err < st->tol) {
+        if (w0) st->iter += 1;
+        finish(st, 0);
+      }
       break;
     }
     case PH_COMBINE: {
       // beta recurrence against this cycle's columns 0..i-1
-      for (int s = 0; s < i; ++s) {
-        Sc acc = sums[s];
-        for (int u = 0; u < s; ++u) acc = acc + st->beta[u] * st->S[s * NMAX + u];
-        st->beta[s] = zero<Sc>() - sc_div(acc, st->c[s]);
-      }
+      const Sc b = forward_subst(st, sums, 0, i);
+      const int s = threadIdx.x % WAVE;
+      if (s < i) st->beta[s] = b;
       break;
     }
     case PH_SPMV_STEP: {
-      for (int s = i; s < n; ++s) st->S[s * NMAX + i] = sums[s - i];
+      const int l = threadIdx.x % WAVE;
+      if (i + l < n) st->S[(i + l) * NMAX + i] = sums[l];
       Sc ci = sums[0];
-      st->c[i] = ci;
+      if (w0) st->c[i] = ci;
       if (is_zero(ci) || !finite(ci)) { finish(st, -1); break; }
-      st->alpha = sc_div(st->e, ci);
+      if (w0) {
+        st->cinv[i] = sc_div(from_real<Sc>(1.0), ci);
+        st->alpha = sc_div(st->e, ci);
+      }
       break;
     }
     case PH_SPMV_OMEGA: {
@@ -236,91 +288,73 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
         if (a < st->kappa && a != 0.0) om = (st->kappa / a) * om;
       }
       if (is_zero(om) || !finite(om)) { finish(st, -1); break; }
-      st->omega = om;
+      if (w0) st->omega = om;
       break;
     }
     case PH_OMEGA_UPD: {
-      long long k = ++st->iter;
+      const long long k = st->iter + 1;
       double err = sqrt(re(sums[0])) / st->bnrm2;
-      st->err = err;
+      if (w0) {
+        st->iter = k;
+        st->err = err;
+      }
       if (!finite(err)) { finish(st, -1); break; }
       if (err < st->tol) { finish(st, 0); break; }
       if (k >= st->maxit) { finish(st, 1); break; }
       if (stagnated(st, err, k)) { finish(st, 2); break; }
-      st->e = sums[1];                       // e = q_1^H r
+      if (w0) st->e = sums[1];               // e = q_1^H r
       beta_tilde(st, sums + 1, 0, n);
       break;
     }
   }
 }
 
-// Sums rows [r0, r1) of a pass's partials (row length STRIDE; at most
-// MAX_PARTIAL_ROWS rows) into sums[0..nsum) in LDS, in a fixed order: lane-
-// strided over the rows, then a tree over lanes and a fixed sweep over waves.
-// All loads of a lane are issued before any is added where the registers allow
-// (a compile-time trip count).  Ends with a barrier; every thread must call it.
-template <class Sc, int STRIDE>
+// Sums rows [r0, r1) of a pass's partials (row length STRIDE) into
+// sums[0..nsum) in LDS, in a fixed order.  Thread (g, d) of the workgroup
+// (d = t % STRIDE, g = t / STRIDE, G = BLOCK / STRIDE groups) adds entry d of
+// rows g, g + G, g + 2G, ... in that order, with 8 loads in flight (adjacent
+// threads read adjacent words); the G group sums of each entry are then added
+// in group order.  MAXR is the most rows a call sees: each thread then loads
+// all its rows in one batch.  Ends with a barrier; every thread must call it.
+template <class Sc, int STRIDE, int MAXR>
 __device__ void sum_rows(const Sc* __restrict__ partial, int r0, int r1, int nsum, Sc* sums) {
-  __shared__ Sc red2[BLOCK / WAVE][STRIDE];
-  const int lane = threadIdx.x % WAVE, wid = threadIdx.x / WAVE;
+  constexpr int G = BLOCK / STRIDE;
+  constexpr int U = (MAXR + G - 1) / G;   // rows loaded together
+  __shared__ Sc red[G][STRIDE];
+  const int t = threadIdx.x, d = t % STRIDE, g = t / STRIDE;
   const int nrows = r1 - r0;
-  Sc acc[STRIDE];
+  if (g < G && d < nsum) {
+    const Sc* base = partial + (size_t)r0 * STRIDE + d;
+    Sc acc = zero<Sc>();
+    for (int k0 = g; k0 < nrows; k0 += U * G) {
+      Sc v[U];
 #pragma unroll
-  for (int d = 0; d < STRIDE; ++d) acc[d] = zero<Sc>();
-  constexpr int KR = MAX_PARTIAL_ROWS / BLOCK;                  // rows per lane at most
-  constexpr int WORDS = (int)(STRIDE * sizeof(Sc) / 8);
-  if constexpr (WORDS > 32) {
-    // long rows: the accumulators alone take half the register file, so each
-    // row is summed as it arrives
-    for (int b = threadIdx.x; b < nrows; b += BLOCK) {
-      const Sc* row = partial + (size_t)(r0 + b) * STRIDE;
-#pragma unroll
-      for (int d = 0; d < STRIDE; ++d)
-        if (d < nsum) add_(acc[d], row[d]);
-    }
-  } else {
-    constexpr int KC = WORDS <= 8 ? KR : WORDS <= 16 ? 2 : 1;   // rows loaded together
-#pragma unroll
-    for (int k0 = 0; k0 < KR; k0 += KC) {
-      if (k0 * BLOCK >= nrows) break;   // uniform
-      Sc v[KC][STRIDE];
-#pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        const int b = threadIdx.x + (k0 + k) * BLOCK;
-        // rows past the range re-read its first row and entries past nsum are
-        // read unused: the buffer holds STRIDE entries for every row
-        const Sc* row = partial + (size_t)(r0 + (b < nrows ? b : 0)) * STRIDE;
-#pragma unroll
-        for (int d = 0; d < STRIDE; ++d) v[k][d] = row[d];
+      for (int u = 0; u < U; ++u) {
+        const int r = k0 + u * G;
+        v[u] = base[(size_t)(r < nrows ? r : 0) * STRIDE];   // row 0 of the range re-read, unused
       }
 #pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        const bool on = threadIdx.x + (k0 + k) * BLOCK < nrows;
-#pragma unroll
-        for (int d = 0; d < STRIDE; ++d)
-          if (on && d < nsum) add_(acc[d], v[k][d]);
-      }
+      for (int u = 0; u < U; ++u)
+        if (k0 + u * G < nrows) add_(acc, v[u]);
     }
+    red[g][d] = acc;
   }
-#pragma unroll
-  for (int d = 0; d < STRIDE; ++d) {
-    if (d < nsum) {
-      Sc v = wave_sum(acc[d]);
-      if (lane == 0) red2[wid][d] = v;
-    }
-  }
-  __syncthreads();   // every wave's red2 row is written before any lane sums across waves
-  if (threadIdx.x < nsum) {
-    Sc v = red2[0][threadIdx.x];
-    for (int w = 1; w < BLOCK / WAVE; ++w) add_(v, red2[w][threadIdx.x]);
-    sums[threadIdx.x] = v;
+  __syncthreads();
+  if (t < nsum) {
+    Sc v = red[0][t];
+    for (int q = 1; q < G; ++q) add_(v, red[q][t]);
+    sums[t] = v;
   }
   __syncthreads();
 }
 
-// First stage for long partial rows (many shadow vectors, complex): workgroup
-// g sums the g-th contiguous share of the rows into row g of `out`, so that
-// the one-workgroup stage reads gridDim.x rows instead of nblocks.
+// Partial rows longer than 64 bytes (many shadow vectors, complex) are summed
+// in two stages: PSUM_GRID workgroups first.
+template <class Sc, int STRIDE>
+constexpr bool two_stage() { return STRIDE * sizeof(Sc) > 64; }
+
+// First stage: workgroup g sums the g-th contiguous share of the rows into row
+// g of `out`, so that the one-workgroup stage reads PSUM_GRID rows.
 template <class Sc, int STRIDE>
 __global__ __launch_bounds__(BLOCK) void k_psum(const State<Sc>* st, const Sc* __restrict__ partial, int nblocks,
                                                 int nsum, Sc* __restrict__ out) {
@@ -328,12 +362,12 @@ __global__ __launch_bounds__(BLOCK) void k_psum(const State<Sc>* st, const Sc* _
   __shared__ Sc sums[STRIDE];
   const int r0 = (int)((long long)nblocks * blockIdx.x / gridDim.x);
   const int r1 = (int)((long long)nblocks * (blockIdx.x + 1) / gridDim.x);
-  sum_rows<Sc, STRIDE>(partial, r0, r1, nsum, sums);
+  sum_rows<Sc, STRIDE, (MAX_PARTIAL_ROWS + PSUM_GRID - 1) / PSUM_GRID>(partial, r0, r1, nsum, sums);
   if (threadIdx.x < nsum) out[(size_t)blockIdx.x * STRIDE + threadIdx.x] = sums[threadIdx.x];
 }
 
 // One workgroup: sum the partials of the previous pass (or of k_psum) in a
-// fixed order and run the coefficient recurrence on one lane.  The state is
+// fixed order and run the coefficient recurrence on one wave.  The state is
 // staged in LDS for the recurrence (its loops read the n x n Gram matrix and
 // the coefficient lists entry by entry) and written back afterwards; rows
 // s >= n of the Gram matrix are never touched and stay out of both copies.
@@ -348,8 +382,9 @@ __global__ __launch_bounds__(BLOCK) void k_scalar(State<Sc>* st, const Sc* __res
   unsigned long long* gw = reinterpret_cast<unsigned long long*>(st);
   unsigned long long* lw = reinterpret_cast<unsigned long long*>(&ss);
   for (int w = threadIdx.x; w < nwords; w += BLOCK) lw[w] = gw[w];
-  sum_rows<Sc, STRIDE>(partial, 0, nblocks, nsum, sums);   // its barriers also order the copy
-  if (threadIdx.x == 0) scalar_program(&ss, sums, phase, i, j, n);
+  constexpr int MAXR = two_stage<Sc, STRIDE>() ? PSUM_GRID : MAX_PARTIAL_ROWS;
+  sum_rows<Sc, STRIDE, MAXR>(partial, 0, nblocks, nsum, sums);   // its barriers also order the copy
+  if (threadIdx.x < WAVE) scalar_program(&ss, sums, phase, i, j, n);
   __syncthreads();
   for (int w = threadIdx.x; w < nwords; w += BLOCK) gw[w] = lw[w];
 }
