@@ -101,7 +101,8 @@ def bench_serving(args, torch, workloads, binding):
         it[4].zero_()
     torch.cuda.synchronize()
 
-    server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight)
+    server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight,
+                            small_n_max=args.small_n_max)
     t0 = time.perf_counter()
     tickets = []
     for r, p, dA, b, x, Q in items:
@@ -121,6 +122,20 @@ def bench_serving(args, torch, workloads, binding):
     server.close()
     log(f"[bench] serving: {len(items)} requests in {makespan:.2f} s, peak concurrency {st.peak_running}, "
         f"peak footprint {st.peak_used_bytes / 1e9:.2f} GB, max true residual {max(errs):.2e}")
+
+    # capacity: the same requests all submitted at once (no arrival gaps)
+    for it in items:
+        it[4].zero_()
+    torch.cuda.synchronize()
+    server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight,
+                            small_n_max=args.small_n_max)
+    t2 = time.perf_counter()
+    tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
+               for r, p, dA, b, x, Q in items]
+    sat_flags = [server.wait(tk)[0].flag for tk in tickets]
+    saturated = time.perf_counter() - t2
+    server.close()
+    log(f"[bench] saturated: {len(items)} requests in {saturated:.2f} s ({len(items) / saturated:.1f} solves/s)")
 
     # the same requests as plain fp64 solves, one after another
     for it in items:
@@ -144,11 +159,14 @@ def bench_serving(args, torch, workloads, binding):
         "config": {"workload": f"serving_poisson200_{len(items)}req", "requests": len(items),
                    "arrival_rate_per_s": 200.0, "N_range": [int(min(r.N for r in reqs)), int(max(r.N for r in reqs))],
                    "inflight": args.inflight, "budget_gb": args.budget_gb, "tol": 1e-10,
+                   "small_n_max": args.small_n_max,
                    "all_converged": bool(all(f == 0 for f in flags)), "max_err_true": float(max(errs)),
                    "total_iterations": int(sum(iters))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "peak_concurrency": int(st.peak_running), "peak_footprint_bytes": int(st.peak_used_bytes),
+        "saturated": {"seconds": saturated, "solves_per_s": len(items) / saturated,
+                      "all_converged": bool(all(f == 0 for f in sat_flags))},
         "sequential_fp64": {"seconds": seq, "solves_per_s": len(items) / seq, "max_err_true": seq_err},
     }
 
@@ -162,6 +180,8 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="serving: first requests of the seeded trace")
     ap.add_argument("--inflight", type=int, default=8, help="serving: solves in flight")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM admission budget")
+    ap.add_argument("--small-n-max", type=int, default=0,
+                    help="serving: largest N batched in one-workgroup launches (0 = library default, -1 = none)")
     ap.add_argument("--serve-precision", default="fp64", choices=["fp64", "ir"],
                     help="serving: iteration precision (fp32-IR doubles the iteration count on these systems)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "ir"])

@@ -146,6 +146,25 @@ int mlbicgstab_workspace_size(const mlb_matrix* A, const mlb_options* opt, size_
  */
 int mlbicgstab_solve(mlb_handle h, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res);
 
+/*
+ * Solve `count` prepared systems in one launch, one workgroup per system: the
+ * whole iteration of Algorithm 7.1 (M = I) of system k runs in workgroup k,
+ * with workgroup barriers where the multi-launch solve has kernel boundaries
+ * (an addition of this library, for many small systems, whose multi-launch
+ * iteration is bound by launch latency rather than bandwidth).  Every h[k]
+ * must come from mlbicgstab_create with a CSR matrix of at most
+ * MLB_BATCH_MAX_N rows, MLB_PREC_FP64 and MLB_PRECOND_NONE (an iterate
+ * record is kept as in a solve); all on the same stream and of the same value type (else
+ * MLB_EINVAL / MLB_EUNSUPPORTED, and nothing runs).  b[k], x[k], Q[k], ldq[k]
+ * and res[k] (res may be NULL) as in mlbicgstab_solve.  A system's result
+ * does not depend on the other systems of the batch.  Synchronises the
+ * stream.  Returns 0 (each flag is in res[k].flag) or an API error.
+ */
+#define MLB_BATCH_MAX_N 262144
+#define MLB_BATCH_MAX 65535
+int mlbicgstab_solve_batch(const mlb_handle* h, int32_t count, const void* const* b, void* const* x,
+                           const void* const* Q, const int64_t* ldq, mlb_result* res);
+
 /* Free everything create() allocated.  NULL is accepted. */
 int mlbicgstab_destroy(mlb_handle h);
 
@@ -176,13 +195,19 @@ enum {
  * the paper's setting is one solve at a time, or a sequence of systems in
  * Section 5.2).
  *
- * A server owns max_inflight workers, each with its own HIP stream.  Requests
- * are admitted first-in first-out: the oldest waiting request starts as soon
- * as a worker is free and its device footprint (mlbicgstab_workspace_size)
- * fits the unused part of budget_bytes.  Requests that arrive while others run
- * therefore start as slots and memory free up, and their kernels overlap on
- * the device.  A solve gives the same result as it would alone (same grids,
- * same reduction order).  The caller's A arrays, b, x and Q of a request must
+ * A server owns max_inflight workers, each with its own HIP stream, and (when
+ * small_n_max >= 0) two batchers with a stream each.  Small requests (CSR,
+ * fp64, no preconditioner, no iterate record, N <= small_n_max) wait for the
+ * batchers; a free batcher takes every waiting small request that fits (at
+ * most 256) and solves them in one launch of mlbicgstab_solve_batch's kernel.
+ * Other requests wait for the workers, which run create, solve and destroy
+ * one request at a time.  Both queues are first-in first-out: the oldest
+ * waiting request starts as soon as a worker (batcher) is free and its device
+ * footprint (mlbicgstab_workspace_size) fits the unused part of budget_bytes.
+ * Requests that arrive while others run therefore start as slots and memory
+ * free up, and their kernels overlap on the device.  A solve gives the same
+ * result whatever else is in flight (same grids and reduction order; the
+ * systems of a batch are independent).  The caller's A arrays, b, x and Q of a request must
  * stay allocated, and x untouched, until the request has been collected.
  * Work is not ordered with any caller stream: the caller must have finished
  * writing b, x and Q (e.g. synchronised its stream) before submitting.
@@ -191,8 +216,12 @@ typedef struct mlb_server* mlb_server_handle;
 
 typedef struct {
   uint64_t budget_bytes;    /* HBM admission budget for the requests' footprints */
-  int32_t max_inflight;     /* workers = solves in flight, 1..64              */
+  int32_t max_inflight;     /* workers = multi-launch solves in flight, 1..64  */
+  int32_t small_n_max;      /* CSR fp64 requests without preconditioner and with
+                               at most this many rows go to the batchers
+                               (0: MLB_SERVER_SMALL_N, -1: none)              */
 } mlb_server_options;
+#define MLB_SERVER_SMALL_N 4096
 
 typedef struct {
   double queued_ms;         /* submit -> start                                  */

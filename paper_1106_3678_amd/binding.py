@@ -64,7 +64,7 @@ class mlb_result(ctypes.Structure):
 
 
 class mlb_server_options(ctypes.Structure):
-    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32)]
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32), ("small_n_max", ctypes.c_int32)]
 
 
 class mlb_request_timing(ctypes.Structure):
@@ -110,6 +110,10 @@ _lib.mlbicgstab_last_error.argtypes = []
 _lib.mlbicgstab_last_error.restype = ctypes.c_char_p
 _lib.mlbicgstab_time_kernel.argtypes = [mlb_handle, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
 _lib.mlbicgstab_time_kernel.restype = ctypes.c_int
+_lib.mlbicgstab_solve_batch.argtypes = [ctypes.POINTER(mlb_handle), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(mlb_result)]
+_lib.mlbicgstab_solve_batch.restype = ctypes.c_int
 _lib.mlb_server_create.argtypes = [ctypes.POINTER(mlb_server_options), ctypes.POINTER(mlb_server_handle)]
 _lib.mlb_server_create.restype = ctypes.c_int
 _lib.mlb_server_submit.argtypes = [mlb_server_handle, ctypes.POINTER(mlb_matrix), ctypes.POINTER(mlb_options),
@@ -160,6 +164,17 @@ def mlbicgstab_solve(h, b_ptr: int, x_ptr: int, q_ptr: int, ldq: int) -> mlb_res
     return res
 
 
+def mlbicgstab_solve_batch(handles, b_ptrs, x_ptrs, q_ptrs, ldqs):
+    """One launch for all systems (one workgroup each); returns the list of mlb_result."""
+    k = len(handles)
+    hs = (mlb_handle * k)(*handles)
+    ptrs = lambda v: (ctypes.c_void_p * k)(*[ctypes.c_void_p(p) for p in v])
+    res = (mlb_result * k)()
+    _check(_lib.mlbicgstab_solve_batch(hs, k, ptrs(b_ptrs), ptrs(x_ptrs), ptrs(q_ptrs), (ctypes.c_int64 * k)(*ldqs),
+                                       res))
+    return list(res)
+
+
 def mlbicgstab_destroy(h) -> int:
     return _check(_lib.mlbicgstab_destroy(h))
 
@@ -174,9 +189,10 @@ def mlbicgstab_time_kernel(h, kernel: int, reps: int) -> float:
     return ms.value
 
 
-def mlb_server_create(budget_bytes: int, max_inflight: int):
+def mlb_server_create(budget_bytes: int, max_inflight: int, small_n_max: int = 0):
     h = mlb_server_handle()
-    _check(_lib.mlb_server_create(ctypes.byref(mlb_server_options(budget_bytes, max_inflight)), ctypes.byref(h)))
+    _check(_lib.mlb_server_create(ctypes.byref(mlb_server_options(budget_bytes, max_inflight, small_n_max)),
+                                  ctypes.byref(h)))
     return h
 
 
@@ -293,6 +309,9 @@ class Solver:
         ldq = Q.stride(1) if self.n > 1 else N
         return mlbicgstab_solve(self.h, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
 
+    def ldq_of(self, Q):
+        return Q.stride(1) if self.n > 1 else self.dmat.nrows
+
     def time_kernel(self, kernel: int, reps: int) -> float:
         return mlbicgstab_time_kernel(self.h, kernel, reps)
 
@@ -308,11 +327,23 @@ class Solver:
             pass
 
 
+def solve_batch(solvers, bs, xs, Qs):
+    """mlbicgstab_solve_batch over Solver objects (same stream, CSR, fp64, no preconditioner)."""
+    for sv, b, x, Q in zip(solvers, bs, xs, Qs):
+        N = sv.dmat.nrows
+        if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != sv.n or Q.stride(0) != 1:
+            raise ValueError("Q must be an N x n column-major tensor")
+        if b.numel() != N or x.numel() != N or not x.is_contiguous() or not b.is_contiguous():
+            raise ValueError("b and x must be contiguous vectors of length N")
+    return mlbicgstab_solve_batch([sv.h for sv in solvers], [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
+                                  [Q.data_ptr() for Q in Qs], [sv.ldq_of(Q) for sv, Q in zip(solvers, Qs)])
+
+
 class Server:
     """Continuous-batching front end: submit() solves, wait()/poll() for their results."""
 
-    def __init__(self, budget_bytes: int, max_inflight: int = 4):
-        self.h = mlb_server_create(budget_bytes, max_inflight)
+    def __init__(self, budget_bytes: int, max_inflight: int = 4, small_n_max: int = 0):
+        self.h = mlb_server_create(budget_bytes, max_inflight, small_n_max)
         self._keep = {}
 
     def submit(self, dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,

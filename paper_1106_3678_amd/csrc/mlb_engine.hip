@@ -30,6 +30,7 @@
 #include "../../include/mlbicgstab.h"
 #include "mlb_kernels.hpp"
 #include "mlb_spmv.hpp"
+#include "mlb_small.hpp"
 #include "mlb_precond.hpp"
 #include "mlb_transpose.hpp"
 
@@ -963,6 +964,123 @@ static int solve_solver(mlb_solver* h, const void* b, void* x, const void* Q, in
   return rc;
 }
 
+// ------------------------------------------------------------------ batched small solves
+
+// Which prepared solvers the one-workgroup batch kernel takes.
+static void check_batchable(const mlb_solver* h) {
+  if (h->format != MLB_CSR) throw Error{MLB_EUNSUPPORTED, "batched solves take CSR matrices"};
+  if (h->opt.precision != MLB_PREC_FP64) throw Error{MLB_EUNSUPPORTED, "batched solves run in fp64"};
+  if (h->opt.precond != MLB_PRECOND_NONE) throw Error{MLB_EUNSUPPORTED, "batched solves take no preconditioner"};
+  if (h->N > MLB_BATCH_MAX_N) throw Error{MLB_EUNSUPPORTED, "batched solves take at most MLB_BATCH_MAX_N rows"};
+}
+
+template <class V64, int NB>
+static void launch_small(const SmallJob<V64, typename traits<V64>::wide>* dj, int count, hipStream_t s) {
+  k_small<V64, typename traits<V64>::wide, NB><<<count, SB, 0, s>>>(dj);
+}
+
+// Runs the systems of hs (same dtype, same stream) in one launch of k_small and
+// fills res[k] as mlbicgstab_solve would.
+template <class V64, class V32>
+static void batch_impl(mlb_solver* const* hs, int count, const void* const* b, void* const* x,
+                       const void* const* Q, const int64_t* ldq, mlb_result* res,
+                       Impl<V64, V32>* (*impl_of)(mlb_solver*)) {
+  using Sc = typename traits<V64>::wide;
+  hipStream_t s = hs[0]->s;
+  std::vector<SmallJob<V64, Sc>> jobs((size_t)count);
+  int nb = 4;
+  for (int k = 0; k < count; ++k) {
+    Engine<V64>& e = impl_of(hs[k])->e64;
+    SmallJob<V64, Sc>& J = jobs[(size_t)k];
+    J.N = e.N;
+    J.n = e.n;
+    J.rp = e.A.rp;
+    J.ci = e.A.ci;
+    J.val = e.A.val;
+    J.rpT = e.AH.rp;
+    J.ciT = e.AH.ci;
+    J.valT = e.AH.val;
+    J.b = (const V64*)b[k];
+    J.x = (V64*)x[k];
+    J.Q = (const V64*)Q[k];
+    J.ldq = ldq[k];
+    J.G = e.G;
+    J.W = e.W;
+    J.F = e.F;
+    J.r = e.r;
+    J.gt = e.gt;
+    J.z = e.z;
+    J.st = e.st;
+    J.tol = hs[k]->opt.tol;
+    J.kappa = hs[k]->opt.kappa;
+    J.maxit = hs[k]->opt.maxit;
+    J.host_done = e.host_done_dev;
+    J.xrec = (V64*)hs[k]->opt.iterates;
+    J.K = hs[k]->opt.record_iterates > 0 ? std::min<long long>(hs[k]->opt.record_iterates, hs[k]->opt.maxit) : 0;
+    *(volatile int*)e.host_done = 0;
+    nb = std::max(nb, bucket(e.n));
+  }
+  Allocs tmp(s, false);
+  auto* dj = tmp.get<SmallJob<V64, Sc>>((size_t)count);
+  HIP_TRY(hipMemcpyAsync(dj, jobs.data(), sizeof(SmallJob<V64, Sc>) * count, hipMemcpyHostToDevice, s));
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  HIP_TRY(hipEventRecord(t0, s));
+  switch (nb) {
+    case 4: launch_small<V64, 4>(dj, count, s); break;
+    case 8: launch_small<V64, 8>(dj, count, s); break;
+    case 16: launch_small<V64, 16>(dj, count, s); break;
+    default: launch_small<V64, 32>(dj, count, s); break;
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(t1, s));
+  HIP_TRY(hipEventSynchronize(t1));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  for (int k = 0; k < count; ++k) {
+    Impl<V64, V32>& im = *impl_of(hs[k]);
+    State<Sc> st;
+    HIP_TRY(hipMemcpyAsync(&st, im.e64.st, sizeof(State<Sc>), hipMemcpyDeviceToHost, s));
+    im.e64.resid_sums(im.A0, (const V64*)b[k], (const V64*)x[k], im.r64);
+    double rr, bb;
+    im.e64.read_aux(&rr, &bb);   // synchronises the stream (st is then valid too)
+    mlb_result R{};
+    R.flag = st.done ? st.flag : 1;
+    R.iter = st.iter;
+    R.fp64_iters = st.iter;
+    R.err_recursive = st.err;
+    R.err_true = std::sqrt(rr) / (bb > 0 ? std::sqrt(bb) : 1.0);
+    R.solve_ms = ms;
+    if (res) res[k] = R;
+    hs[k]->solved = true;
+  }
+}
+
+static Impl<double, float>* real_impl(mlb_solver* h) { return h->real.get(); }
+static Impl<cplx<double>, cplx<float>>* cplx_impl(mlb_solver* h) { return h->cpx.get(); }
+
+static int solve_batch(mlb_solver* const* hs, int count, const void* const* b, void* const* x, const void* const* Q,
+                       const int64_t* ldq, mlb_result* res) {
+  if (!hs || !b || !x || !Q || !ldq) throw Error{MLB_EINVAL, "handles, b, x, Q and ldq must be non-NULL"};
+  if (count < 1 || count > MLB_BATCH_MAX) throw Error{MLB_EINVAL, "count must be in [1, MLB_BATCH_MAX]"};
+  for (int k = 0; k < count; ++k) {
+    if (!hs[k]) throw Error{MLB_EINVAL, "a handle is NULL"};
+    if (!b[k] || !x[k] || !Q[k]) throw Error{MLB_EINVAL, "b, x and Q must be device pointers"};
+    if (ldq[k] < hs[k]->N) throw Error{MLB_EINVAL, "ldq must be >= N"};
+    if (hs[k]->s != hs[0]->s) throw Error{MLB_EINVAL, "batched solvers must share one stream"};
+    if (hs[k]->dtype != hs[0]->dtype) throw Error{MLB_EINVAL, "batched solvers must share one value type"};
+    check_batchable(hs[k]);
+  }
+  if (hs[0]->real)
+    batch_impl(hs, count, b, x, Q, ldq, res, real_impl);
+  else
+    batch_impl(hs, count, b, x, Q, ldq, res, cplx_impl);
+  return 0;
+}
+
 }  // namespace mlb
 
 // ------------------------------------------------------------------ C ABI
@@ -1020,6 +1138,11 @@ int mlbicgstab_destroy(mlb_handle h) {
   });
 }
 
+int mlbicgstab_solve_batch(const mlb_handle* h, int32_t count, const void* const* b, void* const* x,
+                           const void* const* Q, const int64_t* ldq, mlb_result* res) {
+  return guarded([&]() -> int { return solve_batch(h, count, b, x, Q, ldq, res); });
+}
+
 const char* mlbicgstab_last_error(void) { return g_last_error.c_str(); }
 
 int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* ms_per_launch) {
@@ -1071,6 +1194,7 @@ struct Request {
   int rc = 0;
   std::string err;
   bool done = false;
+  bool small = false;   // solved by a batcher (one workgroup per system)
 };
 
 struct Server {
@@ -1080,12 +1204,14 @@ struct Server {
   int running = 0, peak_running = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<std::shared_ptr<Request>> queue;
+  std::deque<std::shared_ptr<Request>> queue;        // requests for the workers
+  std::deque<std::shared_ptr<Request>> small_queue;  // requests for the batchers
+  int small_n_max = 0;                                // largest N a batcher takes (0: none)
   std::unordered_map<int64_t, std::shared_ptr<Request>> table;
   int64_t next_ticket = 1;
   int64_t completed = 0;
   bool stopping = false;
-  std::vector<std::thread> workers;
+  std::vector<std::thread> workers, batchers;
   std::string init_error;
 };
 
@@ -1149,6 +1275,129 @@ static void worker_main(Server* S) {
   if (st) (void)hipStreamDestroy(st);
 }
 
+// A batcher takes every waiting small request that fits the budget (FIFO, at
+// most BATCH_CAP), prepares each on its stream (validation, A^H, workspace),
+// solves them all in one launch of the one-workgroup kernel and completes them
+// together.  Requests that arrive meanwhile wait for the next batch of the
+// next free batcher.
+constexpr int BATCH_CAP = 256;
+constexpr int N_BATCHERS = 2;
+
+static void batcher_main(Server* S) {
+  hipStream_t st = nullptr;
+  int* flags = nullptr;
+  bool ok = hipSetDevice(S->device) == hipSuccess && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+            hipHostMalloc((void**)&flags, 2 * BATCH_CAP * sizeof(int), hipHostMallocMapped) == hipSuccess;
+  while (true) {
+    std::vector<std::shared_ptr<Request>> batch;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] {
+        return (S->stopping && S->small_queue.empty()) ||
+               (!S->small_queue.empty() && S->used + S->small_queue.front()->footprint <= S->budget);
+      });
+      if (S->small_queue.empty()) break;   // stopping and drained
+      const double t = now_s();
+      while (!S->small_queue.empty() && (int)batch.size() < BATCH_CAP &&
+             S->used + S->small_queue.front()->footprint <= S->budget) {
+        auto r = S->small_queue.front();
+        S->small_queue.pop_front();
+        S->used += r->footprint;
+        r->t_start = t;
+        batch.push_back(r);
+      }
+      S->peak = std::max(S->peak, S->used);
+      S->running += (int)batch.size();
+      S->peak_running = std::max(S->peak_running, S->running);
+    }
+    S->cv_work.notify_all();
+    if (!ok) {
+      for (auto& r : batch) {
+        r->rc = MLB_EHIP;
+        r->err = "serving batcher could not create its stream or pinned flags";
+      }
+    } else {
+      std::vector<std::unique_ptr<mlb_solver>> hs(batch.size());
+      std::vector<mlb_solver*> run;
+      std::vector<const void*> bs, Qs;
+      std::vector<void*> xs;
+      std::vector<int64_t> lds;
+      std::vector<size_t> idx;
+      for (size_t k = 0; k < batch.size(); ++k) {
+        Request& r = *batch[k];
+        try {
+          hs[k] = create_solver(&r.A, &r.opt, st, true, flags + 2 * k);
+          run.push_back(hs[k].get());
+          bs.push_back(r.b);
+          xs.push_back(r.x);
+          Qs.push_back(r.Q);
+          lds.push_back(r.ldq);
+          idx.push_back(k);
+        } catch (const Error& e) {
+          r.rc = e.code;
+          r.err = e.msg;
+        } catch (const std::exception& e) {
+          r.rc = MLB_EHIP;
+          r.err = e.what();
+        }
+      }
+      // one batch per value type (the kernel is instantiated per type)
+      for (int pass = 0; pass < 2 && !run.empty(); ++pass) {
+        std::vector<mlb_solver*> part;
+        std::vector<const void*> pb, pq;
+        std::vector<void*> px;
+        std::vector<int64_t> pl;
+        std::vector<size_t> pi;
+        for (size_t q = 0; q < run.size(); ++q)
+          if ((run[q]->dtype == MLB_C128) == (pass == 1)) {
+            part.push_back(run[q]);
+            pb.push_back(bs[q]);
+            px.push_back(xs[q]);
+            pq.push_back(Qs[q]);
+            pl.push_back(lds[q]);
+            pi.push_back(idx[q]);
+          }
+        if (part.empty()) continue;
+        std::vector<mlb_result> res(part.size());
+        try {
+          solve_batch(part.data(), (int)part.size(), pb.data(), px.data(), pq.data(), pl.data(), res.data());
+          for (size_t q = 0; q < part.size(); ++q) {
+            batch[pi[q]]->res = res[q];
+            batch[pi[q]]->rc = res[q].flag;
+          }
+        } catch (const Error& e) {
+          for (size_t q = 0; q < part.size(); ++q) {
+            batch[pi[q]]->rc = e.code;
+            batch[pi[q]]->err = e.msg;
+          }
+        } catch (const std::exception& e) {
+          for (size_t q = 0; q < part.size(); ++q) {
+            batch[pi[q]]->rc = MLB_EHIP;
+            batch[pi[q]]->err = e.what();
+          }
+        }
+      }
+      for (auto& h : hs) h.reset();
+      (void)hipStreamSynchronize(st);
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      const double t = now_s();
+      for (auto& r : batch) {
+        r->t_done = t;
+        r->done = true;
+        S->used -= r->footprint;
+        S->running--;
+        S->completed++;
+      }
+    }
+    S->cv_work.notify_all();
+    S->cv_done.notify_all();
+  }
+  if (flags) (void)hipHostFree(flags);
+  if (st) (void)hipStreamDestroy(st);
+}
+
 static void fill_timing(const Request& r, mlb_request_timing* t) {
   if (!t) return;
   t->queued_ms = 1e3 * (r.t_start - r.t_submit);
@@ -1169,9 +1418,12 @@ int mlb_server_create(const mlb_server_options* o, mlb_server_handle* out) {
     if (!o || !out) throw Error{MLB_EINVAL, "options and out must be non-NULL"};
     if (o->budget_bytes == 0) throw Error{MLB_EINVAL, "budget_bytes must be > 0"};
     if (o->max_inflight < 1 || o->max_inflight > 64) throw Error{MLB_EINVAL, "max_inflight must be in [1, 64]"};
+    if (o->small_n_max < -1 || o->small_n_max > MLB_BATCH_MAX_N)
+      throw Error{MLB_EINVAL, "small_n_max must be -1, 0 or at most MLB_BATCH_MAX_N"};
     auto S = std::make_unique<mlb_server>();
     S->budget = o->budget_bytes;
     S->max_inflight = o->max_inflight;
+    S->small_n_max = o->small_n_max == 0 ? MLB_SERVER_SMALL_N : std::max(o->small_n_max, 0);
     HIP_TRY(hipGetDevice(&S->device));
     // keep freed stream-ordered memory cached in the pool between requests
     hipMemPool_t pool;
@@ -1181,6 +1433,8 @@ int mlb_server_create(const mlb_server_options* o, mlb_server_handle* out) {
     }
     (void)hipGetLastError();
     for (int w = 0; w < o->max_inflight; ++w) S->workers.emplace_back(worker_main, S.get());
+    if (S->small_n_max > 0)
+      for (int w = 0; w < N_BATCHERS; ++w) S->batchers.emplace_back(batcher_main, S.get());
     *out = S.release();
     return 0;
   });
@@ -1212,7 +1466,9 @@ int mlb_server_submit(mlb_server_handle S, const mlb_matrix* A, const mlb_option
       r->ticket = S->next_ticket++;
       r->t_submit = now_s();
       S->table[r->ticket] = r;
-      S->queue.push_back(r);
+      r->small = A->format == MLB_CSR && opt->precision == MLB_PREC_FP64 && opt->precond == MLB_PRECOND_NONE &&
+                 opt->record_iterates == 0 && A->nrows <= S->small_n_max;
+      (r->small ? S->small_queue : S->queue).push_back(r);
       *ticket = r->ticket;
     }
     S->cv_work.notify_all();
@@ -1260,7 +1516,7 @@ int mlb_server_stats(mlb_server_handle S, mlb_server_stats_t* st) {
     st->budget_bytes = S->budget;
     st->used_bytes = S->used;
     st->peak_used_bytes = S->peak;
-    st->queued = (int64_t)S->queue.size();
+    st->queued = (int64_t)(S->queue.size() + S->small_queue.size());
     st->running = S->running;
     st->peak_running = S->peak_running;
     st->completed = S->completed;
@@ -1277,6 +1533,7 @@ int mlb_server_destroy(mlb_server_handle S) {
     }
     S->cv_work.notify_all();
     for (auto& w : S->workers) w.join();
+    for (auto& w : S->batchers) w.join();
     delete S;
     return 0;
   });

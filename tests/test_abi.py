@@ -29,7 +29,8 @@ def binding():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("mlbicgstab_create", "mlbicgstab_solve", "mlbicgstab_destroy", "mlbicgstab_workspace_size",
-              "mlbicgstab_last_error", "mlbicgstab_time_kernel", "mlb_server_create", "mlb_server_submit",
+              "mlbicgstab_last_error", "mlbicgstab_time_kernel", "mlbicgstab_solve_batch", "mlb_server_create",
+              "mlb_server_submit",
               "mlb_server_poll", "mlb_server_wait", "mlb_server_stats", "mlb_server_destroy"):
         assert f in names
 
@@ -85,6 +86,13 @@ def test_null_handle_paths(binding):
     assert binding.raw_call("mlbicgstab_destroy", None) == 0
     ms = ctypes.c_double()
     assert binding.raw_call("mlbicgstab_time_kernel", None, 0, 1, ctypes.byref(ms)) == binding.MLB_EINVAL
+    # batched solves: NULL arrays and an empty batch are refused before anything runs
+    assert binding.raw_call("mlbicgstab_solve_batch", None, 1, None, None, None, None, None) == binding.MLB_EINVAL
+    hs = (binding.mlb_handle * 1)()
+    ptrs = (ctypes.c_void_p * 1)()
+    lds = (ctypes.c_int64 * 1)(1)
+    assert binding.raw_call("mlbicgstab_solve_batch", hs, 0, ptrs, ptrs, ptrs, lds, None) == binding.MLB_EINVAL
+    assert binding.raw_call("mlbicgstab_solve_batch", hs, 1, ptrs, ptrs, ptrs, lds, None) == binding.MLB_EINVAL
 
 
 def test_workspace_size_model(binding):
@@ -99,8 +107,9 @@ def test_workspace_size_model(binding):
 
 def test_server_rejects_bad_options(binding):
     h = binding.mlb_server_handle()
-    for budget, inflight in [(0, 4), (1 << 30, 0), (1 << 30, 65)]:
-        o = binding.mlb_server_options(budget, inflight)
+    for budget, inflight, small in [(0, 4, 0), (1 << 30, 0, 0), (1 << 30, 65, 0), (1 << 30, 4, -2),
+                                    (1 << 30, 4, (1 << 18) + 1)]:
+        o = binding.mlb_server_options(budget, inflight, small)
         assert binding.raw_call("mlb_server_create", ctypes.byref(o), ctypes.byref(h)) == binding.MLB_EINVAL
         assert h.value is None
     assert binding.raw_call("mlb_server_destroy", None) == 0

@@ -1,5 +1,6 @@
 """Serving (continuous batching through mlb_server_*): every result in a concurrent mix equals the same
-solve run alone, a failing request is isolated, and admission respects the HBM budget."""
+request served alone, a failing request is isolated, and admission respects the HBM budget.  Small CSR
+fp64 requests go to the batchers (one-workgroup kernel), the others to the multi-launch workers."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -39,7 +40,17 @@ def upload(p):
     return dA, b, x, Q
 
 
-def solve_alone(p, prec):
+def solve_alone(p, prec, small_n_max=0):
+    """The request alone in a server of its own (the same routing as in the mix)."""
+    dA, b, x, Q = upload(p)
+    torch.cuda.synchronize()
+    server = binding.Server(budget_bytes=8 << 30, max_inflight=1, small_n_max=small_n_max)
+    res, _ = server.wait(server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec))
+    server.close()
+    return res, x.cpu().numpy()
+
+
+def solve_multi_launch(p, prec):
     dA, b, x, Q = upload(p)
     s = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
     res = s.solve(b, x, Q)
@@ -69,6 +80,34 @@ def test_mix_equals_alone():
         assert res_m.iter == res_a.iter
         assert np.array_equal(xm, x_a), k
         assert oracle.true_error(p.A, xm, p.b) < p.tol
+
+
+def test_workers_only_equal_multi_launch_solves():
+    """With the batchers off every request runs the multi-launch iteration: bitwise its plain solve."""
+    reqs = requests(count=6, seed=3)
+    server = binding.Server(budget_bytes=8 << 30, max_inflight=3, small_n_max=-1)
+    bufs = [upload(p) for p, _ in reqs]
+    torch.cuda.synchronize()
+    tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
+               for (p, prec), (dA, b, x, Q) in zip(reqs, bufs)]
+    results = [server.wait(t) for t in tickets]
+    server.close()
+    for (p, prec), (res, _), (_, _, x, _) in zip(reqs, results, bufs):
+        res_a, x_a = solve_multi_launch(p, prec)
+        assert res.flag == res_a.flag == 0 and res.iter == res_a.iter
+        assert np.array_equal(x.cpu().numpy(), x_a)
+
+
+def test_batched_requests_match_multi_launch():
+    """A small request served by a batcher agrees with the multi-launch solve to rounding."""
+    for p, prec in requests(count=4, seed=17):
+        if prec != binding.MLB_PREC_FP64:
+            continue
+        res, x = solve_alone(p, prec)
+        res_m, x_m = solve_multi_launch(p, prec)
+        assert res.flag == res_m.flag == 0
+        assert abs(res.iter - res_m.iter) <= max(1, int(0.05 * res_m.iter))
+        assert rel(x, x_m) < 1e-6
 
 
 def test_failing_request_is_isolated():
