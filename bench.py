@@ -177,7 +177,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "reservoir", "helmholtz", "serving"])
-    ap.add_argument("--requests", type=int, default=400, help="serving: first requests of the seeded trace")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: first requests of the seeded trace")
     ap.add_argument("--inflight", type=int, default=8, help="serving: solves in flight")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM admission budget")
     ap.add_argument("--small-n-max", type=int, default=0,
@@ -236,9 +236,12 @@ def main():
     x = torch.zeros(p.N, dtype=tdt, device=dev)
     prec = binding.MLB_PREC_FP32_IR if args.precision == "ir" else binding.MLB_PREC_FP64
     use_jacobi = args.precond == "jacobi" or (args.precond == "auto" and args.workload == "reservoir")
+    torch.cuda.synchronize()
+    t_create = time.perf_counter()
     solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=args.inner_tol,
                             precond=binding.MLB_PRECOND_JACOBI if use_jacobi else binding.MLB_PRECOND_NONE)
     torch.cuda.synchronize()
+    create_ms = 1e3 * (time.perf_counter() - t_create)   # validation, A^H (and M^{-1} / fp32 copies)
 
     def step():
         x.zero_()
@@ -313,6 +316,7 @@ def main():
             "flag": int(last.flag),
             "err_true": last.err_true,
             "setup_ms": last.setup_ms,
+            "matrix_setup_ms": create_ms,
         },
         "roofline": {
             "kernel": "k_spmv_csrw / k_spmv (SpMV step: w_i = A g_i with q_s^H w_i, s >= i)",
