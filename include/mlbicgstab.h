@@ -165,6 +165,37 @@ int mlbicgstab_solve(mlb_handle h, const void* b, void* x, const void* Q, int64_
 int mlbicgstab_solve_batch(const mlb_handle* h, int32_t count, const void* const* b, void* const* x,
                            const void* const* Q, const int64_t* ldq, mlb_result* res);
 
+/*
+ * Sequences of systems with the same A (Section 5.2, choice of n): the method
+ * is at its strongest over a sequence of systems, with n chosen automatically
+ * from one system to the next.  A sequence owns one solver whose workspace and
+ * A^H serve every n in [n_min, n_max]; A^H is built once.  opt->n is the n of
+ * the first system.  After each solve the next n follows the paper's rule,
+ * with t1 and t2 the solve times (mlb_result.solve_ms) of the previous and
+ * the current system: n + step if t1 > t2, else n - step, kept in
+ * [n_min, n_max]; after the first system n is kept.  step = 0 fixes n.
+ */
+typedef struct mlb_sequence* mlb_sequence_handle;
+
+/* The rule alone: the n after a system solved with n (t_prev_ms < 0: no
+ * previous system, n is kept).  Returns the next n, or MLB_EINVAL. */
+int32_t mlb_sequence_next_n(int32_t n, double t_prev_ms, double t_cur_ms, int32_t step, int32_t n_min,
+                            int32_t n_max);
+
+/* A as in mlbicgstab_create (borrowed until destroy); opt as there, without an
+ * iterate record.  Errors as mlbicgstab_create, MLB_EINVAL for bad n bounds. */
+int mlb_sequence_create(const mlb_matrix* A, const mlb_options* opt, int32_t n_min, int32_t n_max, int32_t step,
+                        void* hip_stream, mlb_sequence_handle* out);
+
+/* Solve the next system: b, x as in mlbicgstab_solve; Q is N x n_max
+ * (column-major, ldq >= N), of which the first n columns are used.  *n_used
+ * (may be NULL) receives that n.  Returns the flag or an API error. */
+int mlb_sequence_solve(mlb_sequence_handle s, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res,
+                       int32_t* n_used);
+
+/* Free the sequence.  NULL is accepted. */
+int mlb_sequence_destroy(mlb_sequence_handle s);
+
 /* Free everything create() allocated.  NULL is accepted. */
 int mlbicgstab_destroy(mlb_handle h);
 

@@ -114,6 +114,19 @@ _lib.mlbicgstab_solve_batch.argtypes = [ctypes.POINTER(mlb_handle), ctypes.c_int
                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(mlb_result)]
 _lib.mlbicgstab_solve_batch.restype = ctypes.c_int
+mlb_sequence_handle = ctypes.c_void_p
+_lib.mlb_sequence_next_n.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32]
+_lib.mlb_sequence_next_n.restype = ctypes.c_int32
+_lib.mlb_sequence_create.argtypes = [ctypes.POINTER(mlb_matrix), ctypes.POINTER(mlb_options), ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.POINTER(mlb_sequence_handle)]
+_lib.mlb_sequence_create.restype = ctypes.c_int
+_lib.mlb_sequence_solve.argtypes = [mlb_sequence_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.POINTER(mlb_result), ctypes.POINTER(ctypes.c_int32)]
+_lib.mlb_sequence_solve.restype = ctypes.c_int
+_lib.mlb_sequence_destroy.argtypes = [mlb_sequence_handle]
+_lib.mlb_sequence_destroy.restype = ctypes.c_int
 _lib.mlb_server_create.argtypes = [ctypes.POINTER(mlb_server_options), ctypes.POINTER(mlb_server_handle)]
 _lib.mlb_server_create.restype = ctypes.c_int
 _lib.mlb_server_submit.argtypes = [mlb_server_handle, ctypes.POINTER(mlb_matrix), ctypes.POINTER(mlb_options),
@@ -187,6 +200,29 @@ def mlbicgstab_time_kernel(h, kernel: int, reps: int) -> float:
     ms = ctypes.c_double()
     _check(_lib.mlbicgstab_time_kernel(h, kernel, reps, ctypes.byref(ms)))
     return ms.value
+
+
+def mlb_sequence_next_n(n: int, t_prev_ms: float, t_cur_ms: float, step: int, n_min: int, n_max: int) -> int:
+    return _lib.mlb_sequence_next_n(n, t_prev_ms, t_cur_ms, step, n_min, n_max)
+
+
+def mlb_sequence_create(A: mlb_matrix, opt: mlb_options, n_min: int, n_max: int, step: int, hip_stream: int = 0):
+    h = mlb_sequence_handle()
+    _check(_lib.mlb_sequence_create(ctypes.byref(A), ctypes.byref(opt), n_min, n_max, step,
+                                    ctypes.c_void_p(hip_stream), ctypes.byref(h)))
+    return h
+
+
+def mlb_sequence_solve(h, b_ptr: int, x_ptr: int, q_ptr: int, ldq: int):
+    """(result, n used)."""
+    res, n = mlb_result(), ctypes.c_int32()
+    _check(_lib.mlb_sequence_solve(h, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), ctypes.c_void_p(q_ptr),
+                                   ctypes.c_int64(ldq), ctypes.byref(res), ctypes.byref(n)))
+    return res, n.value
+
+
+def mlb_sequence_destroy(h) -> int:
+    return _check(_lib.mlb_sequence_destroy(h))
 
 
 def mlb_server_create(budget_bytes: int, max_inflight: int, small_n_max: int = 0):
@@ -337,6 +373,41 @@ def solve_batch(solvers, bs, xs, Qs):
             raise ValueError("b and x must be contiguous vectors of length N")
     return mlbicgstab_solve_batch([sv.h for sv in solvers], [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
                                   [Q.data_ptr() for Q in Qs], [sv.ldq_of(Q) for sv, Q in zip(solvers, Qs)])
+
+
+class Sequence:
+    """Systems with the same A, n chosen from one system to the next (Section 5.2)."""
+
+    def __init__(self, dmat: DeviceMatrix, n: int, n_min: int, n_max: int, step: int, tol: float = 1e-10,
+                 maxit: int = 1000, kappa: float = 0.0, precision: int = MLB_PREC_FP64, stream=None):
+        import torch
+
+        self.dmat = dmat
+        self.n_max = n_max
+        self.opt = mlb_options(n, tol, maxit, kappa, precision, 0.0, 0, 0, None, MLB_PRECOND_NONE)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = mlb_sequence_create(dmat.descriptor(), self.opt, n_min, n_max, step, self.stream.cuda_stream)
+
+    def solve(self, b, x, Q):
+        """Q: N x n_max column-major.  Returns (result, n used)."""
+        N = self.dmat.nrows
+        if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != self.n_max or Q.stride(0) != 1:
+            raise ValueError("Q must be an N x n_max column-major tensor")
+        if b.numel() != N or x.numel() != N or not x.is_contiguous() or not b.is_contiguous():
+            raise ValueError("b and x must be contiguous vectors of length N")
+        ldq = Q.stride(1) if self.n_max > 1 else N
+        return mlb_sequence_solve(self.h, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
+
+    def close(self):
+        if self.h:
+            mlb_sequence_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -289,24 +289,41 @@ struct Engine {
 
   // ext_flag: a pinned, host-mapped int the caller owns (serving workers reuse one
   // per worker); NULL = allocate one.
-  void init(const Mat<V>& A_, const Mat<V>& AH_, int n_, hipStream_t s_, Allocs& al, int* ext_flag = nullptr) {
+  // n_alloc: the largest n this engine will run (its workspace); the active n is
+  // set by set_n and may change between solves.
+  void init(const Mat<V>& A_, const Mat<V>& AH_, int n_alloc, hipStream_t s_, Allocs& al, int* ext_flag = nullptr) {
     A = A_;
     AH = AH_;
     N = A.nrows;
-    n = n_;
-    nb = bucket(n);
     s = s_;
-    const size_t Nn = (size_t)N * n;
+    const size_t Nn = (size_t)N * n_alloc;
     G = al.get<V>(Nn);
     W = al.get<V>(Nn);
-    F = al.get<V>((size_t)N * std::max(n - 1, 1));
+    F = al.get<V>((size_t)N * std::max(n_alloc - 1, 1));
     r = al.get<V>(N);
     gt = al.get<V>(N);
     z = al.get<V>(N);
     st = al.get<State<Sc>>(1);
-    // One resident round of workgroups: CUs x the SpMV-step kernel's occupancy for
-    // the SpMV passes (no partly filled second round), 8 per CU for the streaming
-    // vector passes; MLB_MAX_GRID caps both.
+    part = al.get<Sc>((size_t)MAX_PARTIAL_ROWS * (NMAX + 1));
+    part2 = al.get<Sc>((size_t)PSUM_GRID * (NMAX + 1));
+    set_n(n_alloc);
+    if (ext_flag) {
+      host_done = ext_flag;
+      own_flag = false;
+    } else {
+      HIP_TRY(hipHostMalloc((void**)&host_done, sizeof(int), hipHostMallocMapped));
+    }
+    *host_done = 0;
+    HIP_TRY(hipHostGetDevicePointer((void**)&host_done_dev, host_done, 0));
+    for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // Active number of shadow vectors (<= the n the workspace was sized for).  The
+  // grids: one resident round of workgroups, CUs x the SpMV-step kernel's
+  // occupancy for the SpMV passes (no partly filled second round), 8 per CU for
+  // the streaming vector passes; MLB_MAX_GRID caps both.
+  void set_n(int n_) {
+    n = n_;
+    nb = bucket(n);
     const int cus = device_cus();
     SpmvArgs<V> probe{};
     int occ = 4;
@@ -318,18 +335,8 @@ struct Engine {
     }
     grid_vec = grid_for(N, std::min(MAX_GRID, 8 * cus));
     grid_spmv = grid_for(A.nbrows, std::min(MAX_GRID, occ * cus));
-    part = al.get<Sc>((size_t)std::max(grid_vec, grid_spmv) * (NMAX + 1));
-    part2 = al.get<Sc>((size_t)PSUM_GRID * (NMAX + 1));
-    if (ext_flag) {
-      host_done = ext_flag;
-      own_flag = false;
-    } else {
-      HIP_TRY(hipHostMalloc((void**)&host_done, sizeof(int), hipHostMallocMapped));
-    }
-    *host_done = 0;
-    HIP_TRY(hipHostGetDevicePointer((void**)&host_done_dev, host_done, 0));
-    for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
+
   void release() {
     if (host_done && own_flag) (void)hipHostFree(host_done);
     host_done = nullptr;
@@ -337,9 +344,9 @@ struct Engine {
       if (e) (void)hipEventDestroy(e);
   }
 
-  static size_t bytes(int N, int n, long long grid) {
+  static size_t bytes(int N, int n) {
     return sizeof(V) * ((size_t)N * (2 * n + std::max(n - 1, 1) + 3)) + sizeof(State<Sc>) +
-           sizeof(Sc) * (size_t)(grid + PSUM_GRID) * (NMAX + 1);
+           sizeof(Sc) * (size_t)(MAX_PARTIAL_ROWS + PSUM_GRID) * (NMAX + 1);
   }
 
   // ---- single launches --------------------------------------------------
@@ -594,6 +601,7 @@ struct mlb_solver {
   bool own_stream = false;
   bool solved = false;
   int* ext_flags = nullptr;   // two pinned host-mapped ints owned by a serving worker, or NULL
+  int n_active = 0;           // shadow vectors of the next solve (<= opt.n, the workspace's)
   Allocs al;
   std::unique_ptr<Impl<double, float>> real;
   std::unique_ptr<Impl<cplx<double>, cplx<float>>> cpx;
@@ -770,12 +778,12 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
   } else {
     // fp32 inner iteration inside fp64 iterative refinement (an addition of this library)
     auto& e32 = im.e32;
-    for (int c = 0; c < o.n; ++c)
+    for (int c = 0; c < h->n_active; ++c)
       k_cast<V32, V64, typename traits<V64>::wide><<<grid_for(N, 4096), BLOCK, 0, h->s>>>(
           im.Q32 + (size_t)c * N, Q + (size_t)c * ldq, N, im.e64.st, 0);
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-6;
     const int max_outer = o.max_outer > 0 ? o.max_outer : 30;
-    const long long window = std::max(300, 20 * o.n);   // stagnation window of the inner iteration
+    const long long window = std::max(300, 20 * h->n_active);   // stagnation window of the inner iteration
     long long used = 0;
     double prev = INFINITY;
     bool fallback = false;
@@ -921,6 +929,7 @@ static std::unique_ptr<mlb_solver> create_solver(const mlb_matrix* A, const mlb_
   h->al.stream = stream;
   h->al.ordered = ordered;
   h->ext_flags = flags;
+  h->n_active = opt->n;
   // validate the index arrays on the device before any kernel relies on them
   {
     Allocs tmp(stream, ordered);
@@ -950,6 +959,20 @@ static std::unique_ptr<mlb_solver> create_solver(const mlb_matrix* A, const mlb_
     create_impl(h.get(), A, *h->cpx);
   }
   return h;
+}
+
+// Number of shadow vectors of the following solves (1 <= n <= the n of create).
+static void set_active_n(mlb_solver* h, int n) {
+  if (n < 1 || n > h->opt.n) throw Error{MLB_EINVAL, "n must be in [1, the n the solver was created with]"};
+  if (n == h->n_active) return;
+  h->n_active = n;
+  if (h->real) {
+    h->real->e64.set_n(n);
+    if (h->real->has32) h->real->e32.set_n(n);
+  } else {
+    h->cpx->e64.set_n(n);
+    if (h->cpx->has32) h->cpx->e32.set_n(n);
+  }
 }
 
 static int solve_solver(mlb_solver* h, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res) {
@@ -1095,17 +1118,16 @@ int mlbicgstab_workspace_size(const mlb_matrix* A, const mlb_options* opt, size_
     const int N = (int)A->nrows;
     const int nbr = A->format == MLB_BSR3 ? N / 3 : N;
     const int bs = A->format == MLB_BSR3 ? 9 : 1;
-    const long long grid = std::max(grid_for(N, MAX_GRID), grid_for(nbr, MAX_GRID));
     const bool c = A->dtype == MLB_C128;
     const size_t sv = c ? 16 : 8;
     size_t t = (size_t)(nbr + 1) * 4 + (size_t)A->nnz * 4 + (size_t)A->nnz * bs * sv;   // A^H
-    t += c ? Engine<cplx<double>>::bytes(N, opt->n, grid) : Engine<double>::bytes(N, opt->n, grid);
+    t += c ? Engine<cplx<double>>::bytes(N, opt->n) : Engine<double>::bytes(N, opt->n);
     t += (size_t)N * sv;                                                                   // r64
     if (opt->precond == MLB_PRECOND_JACOBI)                                                // M, M^{-1}, A M^{-1}
       t += (size_t)nbr * bs * 2 * sv + (size_t)A->nnz * bs * sv;
     if (opt->precision == MLB_PREC_FP32_IR) {
       t += (size_t)A->nnz * bs * sv;                                                       // fp32 A, A^H values
-      t += c ? Engine<cplx<float>>::bytes(N, opt->n, grid) : Engine<float>::bytes(N, opt->n, grid);
+      t += c ? Engine<cplx<float>>::bytes(N, opt->n) : Engine<float>::bytes(N, opt->n);
       t += (size_t)N * (2 + opt->n) * (sv / 2);
     }
     *bytes = t;
@@ -1144,6 +1166,74 @@ int mlbicgstab_solve_batch(const mlb_handle* h, int32_t count, const void* const
 }
 
 const char* mlbicgstab_last_error(void) { return g_last_error.c_str(); }
+
+// ---- sequences of systems with the automatic choice of n (Section 5.2)
+
+int32_t mlb_sequence_next_n(int32_t n, double t_prev_ms, double t_cur_ms, int32_t step, int32_t n_min,
+                            int32_t n_max) {
+  if (step < 0 || n_min < 1 || n_max < n_min || n_max > MLB_MAX_N || n < n_min || n > n_max) return MLB_EINVAL;
+  if (!(t_prev_ms >= 0.0) || !(t_cur_ms >= 0.0)) return n;   // no previous system yet
+  const int32_t m = t_prev_ms > t_cur_ms ? n + step : n - step;
+  return std::min(std::max(m, n_min), n_max);
+}
+
+}  // extern "C"
+
+struct mlb_sequence {
+  std::unique_ptr<mlb_solver> h;
+  int32_t n_min = 1, n_max = 1, step = 1;
+  double t_prev = -1.0;   // solve time of the previous system (ms), < 0 before the first
+};
+
+extern "C" {
+
+int mlb_sequence_create(const mlb_matrix* A, const mlb_options* opt, int32_t n_min, int32_t n_max, int32_t step,
+                        void* hip_stream, mlb_sequence_handle* out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> int {
+    if (!A || !opt || !out) throw Error{MLB_EINVAL, "A, opt and out must be non-NULL"};
+    check_options(opt);
+    if (n_max > MLB_MAX_N) throw Error{MLB_EUNSUPPORTED, "n_max > MLB_MAX_N (32) is not supported"};
+    if (step < 0 || n_min < 1 || n_max < n_min || opt->n < n_min || opt->n > n_max)
+      throw Error{MLB_EINVAL, "need step >= 0 and 1 <= n_min <= opt->n <= n_max"};
+    if (opt->record_iterates > 0) throw Error{MLB_EINVAL, "a sequence records no iterates"};
+    mlb_options o = *opt;
+    o.n = n_max;   // workspace for the largest n
+    auto q = std::make_unique<mlb_sequence>();
+    q->h = create_solver(A, &o, (hipStream_t)hip_stream, false, nullptr);
+    set_active_n(q->h.get(), opt->n);
+    q->n_min = n_min;
+    q->n_max = n_max;
+    q->step = step;
+    *out = q.release();
+    return 0;
+  });
+}
+
+int mlb_sequence_solve(mlb_sequence_handle q, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res,
+                       int32_t* n_used) {
+  return guarded([&]() -> int {
+    if (!q) throw Error{MLB_EINVAL, "sequence is NULL"};
+    mlb_result R{};
+    const int32_t n = q->h->n_active;
+    const int rc = solve_solver(q->h.get(), b, x, Q, ldq, &R);
+    if (res) *res = R;
+    if (n_used) *n_used = n;
+    const double t = R.solve_ms;
+    set_active_n(q->h.get(), mlb_sequence_next_n(n, q->t_prev, t, q->step, q->n_min, q->n_max));
+    q->t_prev = t;
+    return rc;
+  });
+}
+
+int mlb_sequence_destroy(mlb_sequence_handle q) {
+  return guarded([&]() -> int {
+    if (!q) return 0;
+    (void)hipStreamSynchronize(q->h->s);
+    delete q;
+    return 0;
+  });
+}
 
 int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* ms_per_launch) {
   return guarded([&]() -> int {

@@ -30,6 +30,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("mlbicgstab_create", "mlbicgstab_solve", "mlbicgstab_destroy", "mlbicgstab_workspace_size",
               "mlbicgstab_last_error", "mlbicgstab_time_kernel", "mlbicgstab_solve_batch", "mlb_server_create",
+              "mlb_sequence_next_n", "mlb_sequence_create", "mlb_sequence_solve", "mlb_sequence_destroy",
               "mlb_server_submit",
               "mlb_server_poll", "mlb_server_wait", "mlb_server_stats", "mlb_server_destroy"):
         assert f in names
@@ -113,3 +114,36 @@ def test_server_rejects_bad_options(binding):
         assert binding.raw_call("mlb_server_create", ctypes.byref(o), ctypes.byref(h)) == binding.MLB_EINVAL
         assert h.value is None
     assert binding.raw_call("mlb_server_destroy", None) == 0
+
+
+def test_sequence_rule(binding):
+    """Section 5.2: with t1, t2 the times of the previous and the current system, the next system uses
+    n + step if t1 > t2 and n - step otherwise (kept within [n_min, n_max]); no previous time keeps n."""
+    f = binding.mlb_sequence_next_n
+    assert f(4, 10.0, 8.0, 2, 1, 16) == 6       # faster than before: n + step
+    assert f(4, 8.0, 10.0, 2, 1, 16) == 2       # slower: n - step
+    assert f(4, 9.0, 9.0, 2, 1, 16) == 2        # not faster: n - step
+    assert f(15, 10.0, 8.0, 2, 1, 16) == 16     # clamped at n_max
+    assert f(2, 8.0, 10.0, 4, 2, 16) == 2       # clamped at n_min
+    assert f(4, -1.0, 8.0, 2, 1, 16) == 4       # first system: no previous time
+    assert f(4, 10.0, 8.0, 0, 1, 16) == 4       # step 0 fixes n
+    for bad in [(4, 1.0, 2.0, -1, 1, 16), (4, 1.0, 2.0, 1, 0, 16), (4, 1.0, 2.0, 1, 5, 4), (4, 1.0, 2.0, 1, 1, 33),
+                (17, 1.0, 2.0, 1, 1, 16)]:
+        assert f(*bad) == binding.MLB_EINVAL
+
+
+def test_sequence_create_rejects_bad_bounds(binding):
+    A = _desc(binding)
+    h = binding.mlb_sequence_handle()
+    for n, lo, hi, step in [(4, 5, 8, 1), (4, 1, 3, 1), (4, 0, 8, 1), (4, 1, 8, -1)]:
+        o = _opt(binding, n=n)
+        rc = binding.raw_call("mlb_sequence_create", ctypes.byref(A), ctypes.byref(o), lo, hi, step, None,
+                              ctypes.byref(h))
+        assert rc == binding.MLB_EINVAL and h.value is None
+    o = _opt(binding, n=4)
+    assert binding.raw_call("mlb_sequence_create", ctypes.byref(A), ctypes.byref(o), 1, 40, 1, None,
+                            ctypes.byref(h)) == binding.MLB_EUNSUPPORTED
+    res = binding.mlb_result()
+    assert binding.raw_call("mlb_sequence_solve", None, None, None, None, ctypes.c_int64(1), ctypes.byref(res),
+                            None) == binding.MLB_EINVAL
+    assert binding.raw_call("mlb_sequence_destroy", None) == 0
