@@ -171,12 +171,74 @@ def bench_serving(args, torch, workloads, binding):
     }
 
 
+def bench_sequence(args, torch, workloads, binding):
+    """A sequence of systems with the same A (3D convection-diffusion, new b each time): total solve time
+    with n = 1 (BiCGStab), fixed n, and n chosen from one system to the next (Section 5.2)."""
+    m = args.m or 128
+    n_max = 16
+    if args.seq_matrix == "reservoir":
+        p = workloads.config3(n=n_max)
+        name = f"sequence_reservoir_{args.systems}systems"
+        pre = binding.MLB_PRECOND_JACOBI
+    else:
+        p = workloads.config2(n=n_max, m=m)
+        name = f"sequence_convdiff3d_m{m}_{args.systems}systems"
+        pre = binding.MLB_PRECOND_NONE
+    g = np.random.default_rng(1106)
+    rhs = [torch.from_numpy(g.standard_normal(p.N)).cuda() for _ in range(args.systems)]
+    dA = binding.to_device(p.A)
+    Q = binding.column_major(p.Q)
+    x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, n0, lo, hi, step in [("bicgstab_n1", 1, 1, 1, 0), ("fixed_n4", 4, 4, 4, 0), ("fixed_n8", 8, 8, 8, 0),
+                                   ("auto_from_n4_step2", 4, 1, n_max, 2)]:
+        seq = binding.Sequence(dA, n0, lo, hi, step, tol=p.tol, maxit=p.maxit, precond=pre)
+        Qv = Q[:, :hi]
+        x.zero_()
+        seq.solve(rhs[0], x, Qv)   # warm-up (first-use costs), not counted
+        seq.close()
+        seq = binding.Sequence(dA, n0, lo, hi, step, tol=p.tol, maxit=p.maxit, precond=pre)
+        total, used, iters, errs = 0.0, [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in rhs:
+            x.zero_()
+            res, n = seq.solve(b, x, Qv)
+            total += res.solve_ms
+            used.append(n)
+            iters.append(int(res.iter))
+            errs.append(res.err_true)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        seq.close()
+        out[name] = {"solve_ms_total": total, "wall_s": wall, "n_used": used, "iterations": iters,
+                     "max_err_true": max(errs)}
+        log(f"[bench] sequence {name}: {total:.1f} ms over {len(rhs)} systems, n {used}, iterations {iters}")
+    base = out["bicgstab_n1"]["solve_ms_total"]
+    best = min(v["solve_ms_total"] for k, v in out.items() if k != "bicgstab_n1")
+    return {
+        "metric": "time-to-1e-10 residual, sequence of systems", "value": out["auto_from_n4_step2"]["wall_s"],
+        "unit": "s", "n_gpus": 1, "steps": len(rhs), "warmup": 1,
+        "ms_per_step": 1e3 * out["auto_from_n4_step2"]["wall_s"] / len(rhs), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": name, "N": p.N, "tol": p.tol,
+                   "preconditioner": "block Jacobi (right)" if pre else "none"},
+        "variants": out,
+        "reduction_vs_bicgstab": {k: 1.0 - v["solve_ms_total"] / base for k, v in out.items() if k != "bicgstab_n1"},
+        "best_reduction_vs_bicgstab": 1.0 - best / base,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "reservoir", "helmholtz", "serving"])
+    ap.add_argument("--workload", default="convdiff3d",
+                    choices=["convdiff3d", "reservoir", "helmholtz", "serving", "sequence"])
+    ap.add_argument("--systems", type=int, default=10, help="sequence: right-hand sides")
+    ap.add_argument("--seq-matrix", default="convdiff3d", choices=["convdiff3d", "reservoir"],
+                    help="sequence: the matrix (reservoir runs with block Jacobi)")
     ap.add_argument("--requests", type=int, default=2000, help="serving: first requests of the seeded trace")
     ap.add_argument("--inflight", type=int, default=8, help="serving: solves in flight")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM admission budget")
@@ -211,6 +273,9 @@ def main():
     dev = "cuda:0"
     if args.workload == "serving":
         print(json.dumps(bench_serving(args, torch, workloads, binding)), flush=True)
+        return
+    if args.workload == "sequence":
+        print(json.dumps(bench_sequence(args, torch, workloads, binding)), flush=True)
         return
     t = time.perf_counter()
     if args.workload == "convdiff3d":

@@ -379,12 +379,13 @@ class Sequence:
     """Systems with the same A, n chosen from one system to the next (Section 5.2)."""
 
     def __init__(self, dmat: DeviceMatrix, n: int, n_min: int, n_max: int, step: int, tol: float = 1e-10,
-                 maxit: int = 1000, kappa: float = 0.0, precision: int = MLB_PREC_FP64, stream=None):
+                 maxit: int = 1000, kappa: float = 0.0, precision: int = MLB_PREC_FP64, stream=None,
+                 precond: int = MLB_PRECOND_NONE):
         import torch
 
         self.dmat = dmat
         self.n_max = n_max
-        self.opt = mlb_options(n, tol, maxit, kappa, precision, 0.0, 0, 0, None, MLB_PRECOND_NONE)
+        self.opt = mlb_options(n, tol, maxit, kappa, precision, 0.0, 0, 0, None, precond)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.h = mlb_sequence_create(dmat.descriptor(), self.opt, n_min, n_max, step, self.stream.cuda_stream)
 
