@@ -42,6 +42,19 @@ __device__ inline T group_sum(T v) {
   return v;
 }
 
+// The CSR kernels read the column indices and values of A once per pass,
+// coalesced: they are loaded non-temporally, which leaves the caches (L2,
+// Infinity Cache) to the vectors the next passes read again.  (Row pointers,
+// shared by adjacent rows, and the 3x3 blocks of BSR3, read in 72-byte pieces
+// per lane, keep ordinary loads: they rely on cache-line reuse.)
+__device__ inline int ld_stream(const int* p) { return __builtin_nontemporal_load(p); }
+__device__ inline double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ inline float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
+template <class R>
+__device__ inline cplx<R> ld_stream(const cplx<R>* p) {
+  return {ld_stream(&p->re), ld_stream(&p->im)};
+}
+
 // ---------------------------------------------------------------- SpMV tiles
 // A workgroup computes y = A x for a tile of rows into LDS: each wave takes
 // 64 (block) rows, LPR lanes per row, so the column/value streams of one row
@@ -72,15 +85,16 @@ __device__ inline void csr_tile(const int* __restrict__ rp, const int* __restric
     for (int p = 0; p < LPR; ++p) {
       const int q = beg[p] + sub;
       const bool on = q < end[p];
-      col[p] = on ? ci[q] : 0;
-      v[p] = on ? val[q] : zero<V>();
+      col[p] = on ? ld_stream(ci + q) : 0;
+      v[p] = on ? ld_stream(val + q) : zero<V>();
     }
 #pragma unroll
     for (int p = 0; p < LPR; ++p) acc[p] = axpy(zero<V>(), v[p], xin[col[p]]);
     // rows longer than LPR entries
 #pragma unroll
     for (int p = 0; p < LPR; ++p)
-      for (int q = beg[p] + sub + LPR; q < end[p]; q += LPR) acc[p] = axpy(acc[p], val[q], xin[ci[q]]);
+      for (int q = beg[p] + sub + LPR; q < end[p]; q += LPR)
+        acc[p] = axpy(acc[p], ld_stream(val + q), xin[ld_stream(ci + q)]);
 #pragma unroll
     for (int p = 0; p < LPR; ++p) {
 #pragma unroll
@@ -95,7 +109,7 @@ __device__ inline void csr_tile(const int* __restrict__ rp, const int* __restric
       V acc = zero<V>();
       if (row < nrows) {
         const int beg = rp[row], end = rp[row + 1];
-        for (int q = beg + sub; q < end; q += LPR) acc = axpy(acc, val[q], xin[ci[q]]);
+        for (int q = beg + sub; q < end; q += LPR) acc = axpy(acc, ld_stream(val + q), xin[ld_stream(ci + q)]);
       }
 #pragma unroll
       for (int m = LPR / 2; m > 0; m >>= 1) add_(acc, shfl_xor_(acc, m));
@@ -249,15 +263,16 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csrw(State<Sc>* st, Sc* partial,
     for (int p = 0; p < LPR; ++p) {
       const int q = beg[p] + sub;
       const bool on = q < end[p];
-      col[p] = on ? a.ci[q] : 0;
-      v[p] = on ? a.val[q] : zero<V>();
+      col[p] = on ? ld_stream(a.ci + q) : 0;
+      v[p] = on ? ld_stream(a.val + q) : zero<V>();
     }
     V ys[LPR];
 #pragma unroll
     for (int p = 0; p < LPR; ++p) ys[p] = axpy(zero<V>(), v[p], a.xin[col[p]]);
 #pragma unroll
     for (int p = 0; p < LPR; ++p)
-      for (int q = beg[p] + sub + LPR; q < end[p]; q += LPR) ys[p] = axpy(ys[p], a.val[q], a.xin[a.ci[q]]);
+      for (int q = beg[p] + sub + LPR; q < end[p]; q += LPR)
+        ys[p] = axpy(ys[p], ld_stream(a.val + q), a.xin[ld_stream(a.ci + q)]);
     // row sums within each group of LPR lanes (DPP), then the group leaders put
     // them in the wave's LDS slice in row order and lane L reads row row0 + L
 #pragma unroll
