@@ -320,6 +320,16 @@ def column_major(Q, device="cuda"):
     return t.t()
 
 
+def q_layout(Q, N: int, n: int) -> int:
+    """Checks that Q is an N x n column-major tensor (any stride on a dimension of size 1) and returns ldq."""
+    if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != n or (N > 1 and Q.stride(0) != 1):
+        raise ValueError("Q must be an N x n column-major tensor")
+    ldq = Q.stride(1) if n > 1 else N
+    if ldq < N:
+        raise ValueError("Q's columns overlap (leading dimension < N)")
+    return ldq
+
+
 class Solver:
     """One handle: create() on construction, solve() per right-hand side, destroy() on close()."""
 
@@ -338,15 +348,13 @@ class Solver:
 
     def solve(self, b, x, Q) -> mlb_result:
         N = self.dmat.nrows
-        if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != self.n or Q.stride(0) != 1:
-            raise ValueError("Q must be an N x n column-major tensor")
+        ldq = q_layout(Q, N, self.n)
         if b.numel() != N or x.numel() != N or not x.is_contiguous() or not b.is_contiguous():
             raise ValueError("b and x must be contiguous vectors of length N")
-        ldq = Q.stride(1) if self.n > 1 else N
         return mlbicgstab_solve(self.h, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
 
     def ldq_of(self, Q):
-        return Q.stride(1) if self.n > 1 else self.dmat.nrows
+        return q_layout(Q, self.dmat.nrows, self.n)
 
     def time_kernel(self, kernel: int, reps: int) -> float:
         return mlbicgstab_time_kernel(self.h, kernel, reps)
@@ -367,8 +375,7 @@ def solve_batch(solvers, bs, xs, Qs):
     """mlbicgstab_solve_batch over Solver objects (same stream, CSR, fp64, no preconditioner)."""
     for sv, b, x, Q in zip(solvers, bs, xs, Qs):
         N = sv.dmat.nrows
-        if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != sv.n or Q.stride(0) != 1:
-            raise ValueError("Q must be an N x n column-major tensor")
+        q_layout(Q, N, sv.n)
         if b.numel() != N or x.numel() != N or not x.is_contiguous() or not b.is_contiguous():
             raise ValueError("b and x must be contiguous vectors of length N")
     return mlbicgstab_solve_batch([sv.h for sv in solvers], [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
@@ -392,11 +399,9 @@ class Sequence:
     def solve(self, b, x, Q):
         """Q: N x n_max column-major.  Returns (result, n used)."""
         N = self.dmat.nrows
-        if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != self.n_max or Q.stride(0) != 1:
-            raise ValueError("Q must be an N x n_max column-major tensor")
+        ldq = q_layout(Q, N, self.n_max)
         if b.numel() != N or x.numel() != N or not x.is_contiguous() or not b.is_contiguous():
             raise ValueError("b and x must be contiguous vectors of length N")
-        ldq = Q.stride(1) if self.n_max > 1 else N
         return mlb_sequence_solve(self.h, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
 
     def close(self):
@@ -421,10 +426,8 @@ class Server:
     def submit(self, dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
                precision: int = MLB_PREC_FP64, inner_tol: float = 0.0, precond: int = MLB_PRECOND_NONE) -> int:
         N = dmat.nrows
-        if Q.dim() != 2 or Q.shape[0] != N or Q.shape[1] != n or Q.stride(0) != 1:
-            raise ValueError("Q must be an N x n column-major tensor")
+        ldq = q_layout(Q, N, n)
         opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, 0, 0, None, precond)
-        ldq = Q.stride(1) if n > 1 else N
         t = mlb_server_submit(self.h, dmat.descriptor(), opt, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
         self._keep[t] = (dmat, b, x, Q)
         return t

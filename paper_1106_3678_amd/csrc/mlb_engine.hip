@@ -661,6 +661,17 @@ static Mat<V> user_matrix(const mlb_matrix* A) {
 template <class V64, class V32>
 static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& im) {
   Mat<V64> A = user_matrix<V64>(Adesc);
+  if (A.nnz == 0) {
+    // no entries: the caller may pass NULL index / value arrays; give the kernels
+    // valid (never read) ones instead
+    const int bs = A.format == MLB_BSR3 ? 9 : 1;
+    int* ci = h->al.get<int>(1);
+    V64* val = h->al.get<V64>(bs);
+    HIP_TRY(hipMemsetAsync(ci, 0, sizeof(int), h->s));
+    HIP_TRY(hipMemsetAsync(val, 0, sizeof(V64) * bs, h->s));
+    A.ci = ci;
+    A.val = val;
+  }
   im.A0 = A;
   im.bs = A.format == MLB_BSR3 ? 3 : 1;
   if (h->opt.precond == MLB_PRECOND_JACOBI) {
