@@ -152,7 +152,13 @@ static Mat<V> build_transpose(const Mat<V>& A, Allocs& al, hipStream_t s) {
   HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int) * m, s));
   HIP_TRY(hipMemsetAsync(fill, 0, sizeof(int) * m, s));
   if (A.nnz > 0) k_col_count<<<grid_for(A.nnz, 4096), BLOCK, 0, s>>>(A.ci, A.nnz, cnt);
-  k_scan<<<1, SCAN_T, 0, s>>>(cnt, m, rpT);
+  {
+    const int ntiles = (int)((m + SCAN_TILE - 1) / SCAN_TILE);
+    int* tsum = tmp.get<int>((size_t)ntiles + 1);
+    k_scan_tiles<<<ntiles, SCAN_T, 0, s>>>(cnt, m, tsum);
+    k_scan_sums<<<1, SCAN_T, 0, s>>>(tsum, ntiles);
+    k_scan_apply<<<ntiles, SCAN_T, 0, s>>>(cnt, m, tsum, ntiles, rpT);
+  }
   if (bs == 1) {
     k_scatter<V, 1><<<grid_for(m, 4096), BLOCK, 0, s>>>(A.rp, A.ci, A.val, m, rpT, fill, ciT, valT);
     k_sort_rows<V, 1><<<grid_for(m, 4096), BLOCK, 0, s>>>(rpT, m, ciT, valT);

@@ -21,44 +21,78 @@ __global__ void k_col_count(const int* __restrict__ ci, long long nnz, int* __re
     atomicAdd(&cnt[ci[q]], 1);
 }
 
-// Exclusive scan of cnt[0..m) into out[0..m], out[m] = total.  One workgroup
-// of 1024 threads walks the array in chunks of 1024 * 8 entries.
-constexpr int SCAN_T = 1024, SCAN_ITEMS = 8;
-__global__ __launch_bounds__(SCAN_T) void k_scan(const int* __restrict__ cnt, int m, int* __restrict__ out) {
+// Exclusive scan of cnt[0..m) into out[0..m], out[m] = total, in three passes:
+// per-tile sums (tiles of SCAN_TILE entries, one workgroup each), one
+// workgroup scanning the tile sums, then every tile rescanned from its offset.
+constexpr int SCAN_T = 1024, SCAN_ITEMS = 8, SCAN_TILE = SCAN_T * SCAN_ITEMS;
+
+// Inclusive scan of one value per thread across the workgroup (Hillis-Steele in
+// LDS); returns this thread's inclusive prefix, and the total in *total.
+__device__ inline int block_scan_incl(int v, int* part, int* total) {
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < SCAN_T; off <<= 1) {
+    const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const int r = part[threadIdx.x];
+  *total = part[SCAN_T - 1];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tiles(const int* __restrict__ cnt, long long m, int* __restrict__ tsum) {
+  __shared__ int part[SCAN_T];
+  const long long my = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) sum += my + k < m ? cnt[my + k] : 0;
+  int total;
+  block_scan_incl(sum, part, &total);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the ntiles tile sums in place (one workgroup), total in tsum[ntiles].
+__global__ __launch_bounds__(SCAN_T) void k_scan_sums(int* __restrict__ tsum, int ntiles) {
   __shared__ int part[SCAN_T];
   __shared__ int carry_s;
   if (threadIdx.x == 0) carry_s = 0;
   __syncthreads();
-  for (long long base = 0; base < m; base += (long long)SCAN_T * SCAN_ITEMS) {
-    int v[SCAN_ITEMS];
-    int sum = 0;
-    const long long my = base + (long long)threadIdx.x * SCAN_ITEMS;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      v[k] = (my + k < m) ? cnt[my + k] : 0;
-      sum += v[k];
-    }
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the per-thread sums
-    for (int off = 1; off < SCAN_T; off <<= 1) {
-      int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-      __syncthreads();
-      part[threadIdx.x] += add;
-      __syncthreads();
-    }
+  for (int base = 0; base < ntiles; base += SCAN_T) {
+    const int i = base + threadIdx.x;
+    const int v = i < ntiles ? tsum[i] : 0;
+    int total;
+    const int incl = block_scan_incl(v, part, &total);
     const int carry = carry_s;
-    int run = carry + part[threadIdx.x] - sum;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      if (my + k < m) out[my + k] = run;
-      run += v[k];
-    }
+    if (i < ntiles) tsum[i] = carry + incl - v;
     __syncthreads();
-    if (threadIdx.x == SCAN_T - 1) carry_s = carry + part[SCAN_T - 1];
+    if (threadIdx.x == 0) carry_s = carry + total;
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[m] = carry_s;
+  if (threadIdx.x == 0) tsum[ntiles] = carry_s;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(const int* __restrict__ cnt, long long m,
+                                                       const int* __restrict__ toff, int ntiles, int* __restrict__ out) {
+  __shared__ int part[SCAN_T];
+  const long long my = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = my + k < m ? cnt[my + k] : 0;
+    sum += v[k];
+  }
+  int total;
+  int run = toff[blockIdx.x] + block_scan_incl(sum, part, &total) - sum;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (my + k < m) out[my + k] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == ntiles - 1 && threadIdx.x == 0) out[m] = toff[ntiles];
 }
 
 // Scatter entry (row, c) of A to row c of A^H as conj(value) (CSR), or the
