@@ -461,12 +461,13 @@ struct Engine {
 #undef MLB_ALPHA
     if (!(flags & F_SKIP_SCALAR)) scalar(grid_vec, nb + 1, nd + 1, phase, i, j);
   }
-  void combine(int t0, int t1, int nf, int i, int j, int flags = 0) {
+  // out: gt (inner steps) or G_0 (cycle close)
+  void combine(int t0, int t1, int nf, int i, int j, V* out, int flags = 0) {
     flags |= force_flags;
     const Timed tm = timed(MLB_KERNEL_COMBINE);
 #define MLB_COMB(B)                                                                                            \
   MLB_LAUNCH((k_combine<V, Sc, B>), grid_vec, s, tm, st, part, N, (const V*)r, (const V*)W, (const V*)G, (long long)N, \
-             t0, t1, gt, (const V*)F, (long long)N, nf, (int)PH_COMBINE, i, j, n, flags)
+             t0, t1, out, (const V*)F, (long long)N, nf, (int)PH_COMBINE, i, j, n, flags)
     switch (nb) {
       case 4: MLB_COMB(4); break;
       case 8: MLB_COMB(8); break;
@@ -497,8 +498,8 @@ struct Engine {
       // x_{jn+i} = x + alpha g ; r_{jn+i} = r - alpha w ; e = q_{i+1}^H r (and q_s^H r, s > i, when j >= 1)
       alpha(x, i - 1, i, j >= 1 ? n - i : 1, PH_INNER, i, j, xrec, K);
       // g = z_w - g/omega from the previous cycle's columns (j >= 1), or g = r (j = 0); f_s^H g, s < i
-      if (j >= 1) combine(i, n, i, i, j);
-      else combine(i, i, i, i, j);
+      if (j >= 1) combine(i, n, i, i, j, gt);
+      else combine(i, i, i, i, j, gt);
       // g_{jn+i} = g + sum beta_s g_s ; w_{jn+i} = A g_{jn+i} ; c and S column i
       gcomb(gt, i);
       spmv_step(G + (size_t)i * N, i);
@@ -507,8 +508,8 @@ struct Engine {
     alpha(x, n - 1, 0, 0, PH_HALF, n, j, xrec, K);
     spmv_omega(r, z);
     omega_update(x, xrec, K);
-    combine(0, n, 0, 0, j);
-    spmv_step(gt, 0);
+    combine(0, n, 0, 0, j, G);   // g_{jn+n} straight into G_0 (no copy in the SpMV)
+    spmv_step(G, 0);
   }
 
   struct Out {

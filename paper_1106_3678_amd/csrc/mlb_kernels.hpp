@@ -423,10 +423,12 @@ __global__ __launch_bounds__(BLOCK) void k_alpha(State<Sc>* st, Sc* partial, int
 }
 
 // g = r + sum_{s in [t0, n)} (t_s W_s + tg_s G_s) -> gout ; sums: f_s^H g, s < nf.
+// gout may be one of the G columns read (the cycle close writes g_{jn+n} over
+// column 0): every row is read before the same thread writes it.
 template <class V, class Sc, int ND>
 __global__ __launch_bounds__(BLOCK) void k_combine(State<Sc>* st, Sc* partial, int N, const V* __restrict__ r,
-                                                   const V* __restrict__ Wb, const V* __restrict__ Gb, long long ldw,
-                                                   int t0, int t1, V* __restrict__ gout, const V* __restrict__ F,
+                                                   const V* __restrict__ Wb, const V* Gb, long long ldw,
+                                                   int t0, int t1, V* gout, const V* __restrict__ F,
                                                    long long ldf, int nf, int phase, int i, int j, int n, int flags) {
   if (!(flags & F_IGNORE_DONE) && st->done) return;
   V acc[ND > 0 ? ND : 1];
