@@ -32,22 +32,22 @@ def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False):
     averaged over the launches i = 0..n-1 of one cycle.
 
     Matrix: values + column indices + row pointers, each read once; vectors: the
-    gathered input once, n - i columns of Q, the written w_i, and at i = 0 (cycle
-    close) the copy of the input into column 0 of G.
+    gathered input once, n - i columns of Q and the written w_i.  (The input is
+    already in its column of G: the cycle close writes g into G_0 itself.)
     """
     mat = nnz * ((9 if bsr else 1) * sv + 4) + 4 * (nbrows + 1)
-    vec_avg = sum(1 + (n - i) + 1 + (1 if i == 0 else 0) for i in range(n)) / n
+    vec_avg = sum(1 + (n - i) + 1 for i in range(n)) / n
     return mat + vec_avg * N * sv
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, root=ROOT):
     """HBM bytes per SpMV-step launch from the committed rocprofv3 counter summary, or None when
     the kernel source has changed since the counters were taken (or no summary exists)."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", f"spmv_step_{workload}.md")
-    src = os.path.join(ROOT, "paper_1106_3678_amd", "csrc", "mlb_spmv.hpp")   # the SpMV kernels
+    path = os.path.join(root, "profiles", f"spmv_step_{workload}.md")
+    src = os.path.join(root, "paper_1106_3678_amd", "csrc", "mlb_spmv.hpp")   # the SpMV kernels
     if not os.path.exists(path):
         return None
     text = open(path).read()

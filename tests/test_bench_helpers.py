@@ -1,0 +1,48 @@
+"""Host-side pieces of bench.py: the algorithmic byte count of the SpMV-step kernel and the rule that
+reports counter traffic only while the SpMV source is the one the counters were taken on."""
+import hashlib
+import os
+
+import bench
+
+
+def test_spmv_step_bytes_by_hand():
+    # CSR: 10 entries, 4 rows, n = 2: matrix 10 * (8 + 4) + 4 * 5 = 140 B; vectors per launch
+    # (input + n - i columns of Q + output), i = 0, 1: 4 and 3, mean 3.5 vectors of 32 B
+    assert bench.spmv_step_bytes(10, 4, 4, 2, 8) == 140 + 3.5 * 32
+    # BSR3: 2 blocks, 2 block rows (N = 6), n = 1: 2 * (72 + 4) + 4 * 3 = 164 B; 3 vectors of 48 B
+    assert bench.spmv_step_bytes(2, 2, 6, 1, 8, bsr=True) == 164 + 3 * 48
+    # complex values double the value bytes only
+    assert bench.spmv_step_bytes(10, 4, 4, 2, 16) == 10 * 20 + 20 + 3.5 * 64
+
+
+def _tree(tmp_path, src_text, recorded_hash, traffic=12345):
+    csrc = tmp_path / "paper_1106_3678_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "mlb_spmv.hpp").write_text(src_text)
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "spmv_step_w.md").write_text(f"# x\n\ntraffic_bytes_per_launch: {traffic}\n"
+                                         f"kernel_source_sha256: {recorded_hash}\n")
+    return str(tmp_path)
+
+
+def test_traffic_reported_only_for_the_measured_source(tmp_path):
+    text = "// spmv kernels\n"
+    good = hashlib.sha256(text.encode()).hexdigest()
+    root = _tree(tmp_path / "a", text, good)
+    assert bench.measured_traffic("w", root=root) == 12345
+    root = _tree(tmp_path / "b", text + "// edited\n", good)
+    assert bench.measured_traffic("w", root=root) is None
+    assert bench.measured_traffic("missing", root=root) is None
+
+
+def test_committed_profiles_parse():
+    """Every committed SpMV-step summary carries a traffic figure and a source hash."""
+    prof = os.path.join(bench.ROOT, "profiles")
+    names = [f for f in os.listdir(prof) if f.startswith("spmv_step_") and f.endswith(".md")]
+    assert names
+    for f in names:
+        text = open(os.path.join(prof, f)).read()
+        assert "traffic_bytes_per_launch:" in text and "kernel_source_sha256:" in text
+        assert "rocprofv3 --kernel-trace --stats" in text and "rocprofv3 --pmc FETCH_SIZE" in text
