@@ -248,14 +248,33 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csrw(State<Sc>* st, Sc* partial,
   const int wslot = (threadIdx.x / WAVE) * WAVE;
   const int wglobal = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
   const int wstride = gridDim.x * (BLOCK / WAVE);
+  // Real values: lane L loads rp[row0 + L] and every lane loads rp[row0 + 64]
+  // (rows past the end read rp[nrows]: empty rows); the bounds of each lane's
+  // rows then come by lane shuffles, and the next tile's pointers are loaded
+  // while the current tile is processed.  Complex values keep one pointer
+  // pair per row and lane: their registers would cut the occupancy.
+  constexpr bool SHUF = sizeof(V) <= 8;
+  auto rp_at = [&](int t, int off) { return a.rp[min((long long)t * WAVE + off, (long long)a.nrows)]; };
+  int rpl = 0, rpn = 0;
+  if (SHUF && wglobal < nwt) {
+    rpl = rp_at(wglobal, lane);
+    rpn = rp_at(wglobal, WAVE);
+  }
   for (int wt = wglobal; wt < nwt; wt += wstride) {
     const int row0 = wt * WAVE;
     int beg[LPR], end[LPR];
 #pragma unroll
     for (int p = 0; p < LPR; ++p) {
-      const int row = row0 + p * RPP + grp;
-      beg[p] = row < a.nrows ? a.rp[row] : 0;
-      end[p] = row < a.nrows ? a.rp[row + 1] : 0;
+      const int idx = p * RPP + grp;   // row - row0
+      if constexpr (SHUF) {
+        beg[p] = __shfl(rpl, idx, WAVE);
+        const int e = __shfl(rpl, (idx + 1) & (WAVE - 1), WAVE);
+        end[p] = idx == WAVE - 1 ? rpn : e;
+      } else {
+        const int row = row0 + idx;
+        beg[p] = row < a.nrows ? a.rp[row] : 0;
+        end[p] = row < a.nrows ? a.rp[row + 1] : 0;
+      }
     }
     int col[LPR];
     V v[LPR];
@@ -265,6 +284,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csrw(State<Sc>* st, Sc* partial,
       const bool on = q < end[p];
       col[p] = on ? ld_stream(a.ci + q) : 0;
       v[p] = on ? ld_stream(a.val + q) : zero<V>();
+    }
+    if (SHUF && wt + wstride < nwt) {
+      rpl = rp_at(wt + wstride, lane);
+      rpn = rp_at(wt + wstride, WAVE);
     }
     V ys[LPR];
 #pragma unroll
