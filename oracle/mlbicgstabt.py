@@ -30,11 +30,25 @@ Control flow and exit codes follow the paper's realisation of the method:
 Extension (not in the paper, shared with the GPU library): a non-finite c_k,
 omega or residual norm is also reported as breakdown (-1).
 
+Transpose-free variant (``transpose_free=True``; an addition of this
+library, the paper prints no such listing): the beta recurrence needs
+f_s^H g = q_s^H (A M^{-1} g), so the product v = A M^{-1} g of the vector that
+enters it is formed first and carried along: beta_s = -q_s^H v / c_s,
+g += beta_s g_s, v += beta_s w_s, and then w_k = v with no further product.
+F and A^H are never formed.  Per iteration this costs (n-1)/2 more saxpys
+than Algorithm 7.1 and (n-1) N less storage, which are the costs Table 4.2
+gives for the paper's second algorithm; that the two are the same algorithm
+cannot be checked from the paper, which only cites its listing.  With a
+preconditioner, hat g = M^{-1} g is formed once more after the recurrence.
+
 Parity pins (CPU tests): Table 2.1; n = 1 equals an independently written
 BiCGStab iterate by iterate (Section 4.3 remark); finite termination for
 n >= N against an LU solve; cycle 0 equals Algorithm 3.1 and every residual
 satisfies eq. (4.1); FOM/GMRES relations via Algorithm 3.1 (Section 3);
-Table 4.3 operation counts per steady cycle.
+Table 4.3 operation counts per steady cycle.  The transpose-free variant:
+Table 4.2 operation counts at M = I, finite termination, iterates of
+Algorithm 7.1 in exact arithmetic (agreement to rounding on well-conditioned
+systems), and w_k = A M^{-1} g_k up to rounding.
 """
 from __future__ import annotations
 
@@ -142,7 +156,8 @@ def _bad(z):
 
 
 def mlbicgstabt(A, b, Q, x0=None, tol=1e-10, maxit=1000, kappa=0.0, precond=None,
-                record_x=0, counter=None, observer=None, q_update=None, summation="blas"):
+                record_x=0, counter=None, observer=None, q_update=None, summation="blas",
+                transpose_free=False):
     """Solve A x = b with ML(n)BiCGStabt; n is the number of columns of Q.
 
     A        : matrix-like supporting ``A @ v`` and ``A.conj().T`` (dense or scipy sparse)
@@ -154,6 +169,7 @@ def mlbicgstabt(A, b, Q, x0=None, tol=1e-10, maxit=1000, kappa=0.0, precond=None
     q_update : test hook realising adaptive shadow vectors (Section 3 FOM/GMRES relations):
                called as q_update(k, r_k) right after r_k is formed in cycle 0 (and with k = 0
                for r_0); a returned vector replaces q_{k+1} before it is first used.
+    transpose_free: the variant described in the module docstring (no A^H, no F)
     """
     A_is_sparse = sp.issparse(A)
     dtype = np.result_type(A.dtype, np.asarray(b).dtype, np.asarray(Q).dtype, np.float64)
@@ -162,9 +178,11 @@ def mlbicgstabt(A, b, Q, x0=None, tol=1e-10, maxit=1000, kappa=0.0, precond=None
     N, n = Q.shape
     if n < 1:
         raise ValueError("n must be >= 1")
-    AH = A.conj().T
-    if A_is_sparse:
-        AH = AH.tocsr()
+    AH = None
+    if not transpose_free:
+        AH = A.conj().T
+        if A_is_sparse:
+            AH = AH.tocsr()
     ops = _Ops(A, precond, counter, summation)
 
     def apply_mh(v):     # M^{-H} v
@@ -197,11 +215,12 @@ def mlbicgstabt(A, b, Q, x0=None, tol=1e-10, maxit=1000, kappa=0.0, precond=None
 
     def set_shadow(col, q):
         Q[:, col] = q
-        if col < n - 1:
+        if col < n - 1 and not transpose_free:
             F[:, col] = apply_mh(AH @ Q[:, col])
 
-    for s in range(n - 1):
-        F[:, s] = apply_mh(AH @ Q[:, s])
+    if not transpose_free:
+        for s in range(n - 1):
+            F[:, s] = apply_mh(AH @ Q[:, s])
     if q_update is not None:
         q0 = q_update(0, r)
         if q0 is not None:
@@ -259,19 +278,33 @@ def mlbicgstabt(A, b, Q, x0=None, tol=1e-10, maxit=1000, kappa=0.0, precond=None
                 g = ops.saxpy(zw, -1.0 / omega, g)    # g = z_w - g / omega_j
                 if observer is not None:
                     observer("zw", k=k, col=i, Q=Q, zw=zw)
-                # beta recurrence against this cycle's g (columns 0..i-1)
+            elif transpose_free:
+                g = r
+            if transpose_free:
+                # beta recurrence with f_s^H g = q_s^H v, v = A M^{-1} g carried along
+                v = ops.matvec(ops.psolve(g))
                 for s in range(0, i):
-                    beta = -ops.dot(F[:, s], g) / c[s]
+                    beta = -ops.dot(Q[:, s], v) / c[s]
                     g = ops.saxpy(g, beta, G[:, s])
+                    v = ops.saxpy(v, beta, W[:, s])
+                G[:, i] = g
+                ghat = g if precond is None else ops.psolve(g)
+                W[:, i] = v                            # w_{jn+i} = A M^{-1} g_{jn+i}, recombined
             else:
-                beta = -ops.dot(F[:, 0], r) / c[0]
-                g = ops.saxpy(r, beta, G[:, 0])
-                for s in range(1, i):
-                    beta = -ops.dot(F[:, s], g) / c[s]
-                    g = ops.saxpy(g, beta, G[:, s])
-            G[:, i] = g
-            ghat = ops.psolve(g)
-            W[:, i] = ops.matvec(ghat)                 # w_{jn+i}
+                if j >= 1:
+                    # beta recurrence against this cycle's g (columns 0..i-1)
+                    for s in range(0, i):
+                        beta = -ops.dot(F[:, s], g) / c[s]
+                        g = ops.saxpy(g, beta, G[:, s])
+                else:
+                    beta = -ops.dot(F[:, 0], r) / c[0]
+                    g = ops.saxpy(r, beta, G[:, 0])
+                    for s in range(1, i):
+                        beta = -ops.dot(F[:, s], g) / c[s]
+                        g = ops.saxpy(g, beta, G[:, s])
+                G[:, i] = g
+                ghat = ops.psolve(g)
+                W[:, i] = ops.matvec(ghat)             # w_{jn+i}
             c[i] = ops.dot(Q[:, i], W[:, i])           # c_{jn+i} = q_{i+1}^H w_{jn+i}
             if observer is not None:
                 observer("w", k=k, col=i, Q=Q, W=W, G=G, F=F)

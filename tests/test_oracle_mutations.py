@@ -2,6 +2,7 @@
 
 The copy is made from the oracle's source text on the CPU; the real oracle is untouched.
 """
+import functools
 import os
 import sys
 import types
@@ -23,8 +24,8 @@ MUTATIONS = {
     # an off-by-one ring index in alpha
     "alpha_index": ("alpha = e / c[i - 1]", "alpha = e / c[i % n]"),
     # a dropped beta recurrence (no A^H)
-    "drop_f_loop": ("beta = -ops.dot(F[:, s], g) / c[s]\n                    g = ops.saxpy(g, beta, G[:, s])\n            else:",
-                    "pass\n            else:"),
+    "drop_f_loop": ("beta = -ops.dot(F[:, s], g) / c[s]\n                        g = ops.saxpy(g, beta, G[:, s])\n                else:",
+                    "pass\n                else:"),
     # a transposed (unconjugated / wrong-side) product for F
     "f_not_transposed": ("F[:, s] = apply_mh(AH @ Q[:, s])", "F[:, s] = apply_mh(A @ Q[:, s])"),
     # the wrong residual in the omega step
@@ -33,9 +34,21 @@ MUTATIONS = {
     "no_conj": ("return np.vdot(u, v)", "return np.dot(u, v)"),
 }
 
+# Slips in the transpose-free variant, checked with the same subset run on that variant.
+TF_MUTATIONS = {
+    # v not carried along the beta recurrence
+    "tf_drop_v_update": ("v = ops.saxpy(v, beta, W[:, s])", "v = v"),
+    # a wrong sign of beta
+    "tf_beta_sign": ("beta = -ops.dot(Q[:, s], v) / c[s]", "beta = ops.dot(Q[:, s], v) / c[s]"),
+    # the wrong shadow vector in the beta recurrence
+    "tf_q_index": ("beta = -ops.dot(Q[:, s], v) / c[s]", "beta = -ops.dot(Q[:, (s + 1) % n], v) / c[s]"),
+    # the product taken before the beta~ recurrence has formed g
+    "tf_product_of_r": ("v = ops.matvec(ops.psolve(g))", "v = ops.matvec(ops.psolve(r))"),
+}
+
 
 def _mutant(name):
-    old, new = MUTATIONS[name]
+    old, new = {**MUTATIONS, **TF_MUTATIONS}[name]
     text = open(SRC).read()
     assert old in text, name
     mod = types.ModuleType(f"oracle_mutant_{name}")
@@ -95,9 +108,17 @@ def _pins_hold(solve):
 def test_unmutated_oracle_passes_the_subset():
     from oracle import mlbicgstabt
     assert _pins_hold(mlbicgstabt)
+    assert _pins_hold(functools.partial(mlbicgstabt, transpose_free=True))
 
 
 @pytest.mark.filterwarnings("ignore::RuntimeWarning")
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_mutation_is_caught(name):
     assert not _pins_hold(_mutant(name)), f"planted slip {name!r} was not caught"
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+@pytest.mark.parametrize("name", sorted(TF_MUTATIONS))
+def test_transpose_free_mutation_is_caught(name):
+    mutant = functools.partial(_mutant(name), transpose_free=True)
+    assert not _pins_hold(mutant), f"planted slip {name!r} was not caught"
