@@ -33,7 +33,9 @@ def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False):
 
     Matrix: values + column indices + row pointers, each read once; vectors: the
     gathered input once, n - i columns of Q and the written w_i.  (The input is
-    already in its column of G: the cycle close writes g into G_0 itself.)
+    already in its column of G: the cycle close writes g into G_0 itself.)  The
+    transpose-free steps read columns 0..i-1 of Q instead (v = A g with q_s^H v,
+    s < i): the same count over a cycle, so the same average.
     """
     mat = nnz * ((9 if bsr else 1) * sv + 4) + 4 * (nbrows + 1)
     vec_avg = sum(1 + (n - i) + 1 for i in range(n)) / n
@@ -250,6 +252,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="number of shadow vectors (0 = the workload's)")
     ap.add_argument("--m", type=int, default=0, help="grid points per dimension (0 = the workload's)")
     ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--transpose-free", action="store_true",
+                    help="iterate without A^H (beta recurrence from q_s^H A g, w recombined)")
     ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi"],
                     help="auto: block Jacobi for the reservoir workload, none otherwise")
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle sample length (iterations)")
@@ -292,6 +296,8 @@ def main():
                    "helmholtz": f"helmholtz_m{args.m or 96}_n{p.n}"}[args.workload]
     if args.precision != "fp64":
         profile_key += "_ir"
+    if args.transpose_free:
+        profile_key += "_tf"
     nbrows = len(p.A.indptr) - 1
     log(f"[bench] generated {p.name}: N={p.N} stored={nnz} in {time.perf_counter() - t:.1f} s")
     dA = binding.to_device(p.A, dev)
@@ -304,7 +310,8 @@ def main():
     torch.cuda.synchronize()
     t_create = time.perf_counter()
     solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=args.inner_tol,
-                            precond=binding.MLB_PRECOND_JACOBI if use_jacobi else binding.MLB_PRECOND_NONE)
+                            precond=binding.MLB_PRECOND_JACOBI if use_jacobi else binding.MLB_PRECOND_NONE,
+                            transpose_free=args.transpose_free)
     torch.cuda.synchronize()
     create_ms = 1e3 * (time.perf_counter() - t_create)   # validation, A^H (and M^{-1} / fp32 copies)
 
@@ -337,8 +344,9 @@ def main():
     achieved = bytes_spmv / (ms_spmv * 1e-3) / 1e9
     ms_alpha = solver.time_kernel(binding.MLB_KERNEL_ALPHA_STEP, args.kernel_reps)
     ms_comb = solver.time_kernel(binding.MLB_KERNEL_COMBINE, args.kernel_reps)
+    ms_recomb = solver.time_kernel(binding.MLB_KERNEL_RECOMBINE, args.kernel_reps)
     log(f"[bench] spmv-step {ms_spmv * 1e3:.1f} us/launch -> {achieved:.0f} GB/s ; alpha {ms_alpha * 1e3:.1f} us ; "
-        f"combine {ms_comb * 1e3:.1f} us")
+        f"combine {ms_comb * 1e3:.1f} us ; recombine {ms_recomb * 1e3:.1f} us")
     solver.close()
     if args.calib_copy > 0:
         # a plain copy kernel of known size: reads and writes calib-copy GiB per launch
@@ -375,11 +383,13 @@ def main():
             "tol": p.tol,
             "precision": args.precision,
             "preconditioner": "block Jacobi (right)" if use_jacobi else "none",
+            "variant": "transpose-free (no A^H)" if args.transpose_free else "Algorithm 7.1 (explicit A^H)",
             "iterations": int(last.iter),
             "outer_iters": int(last.outer_iters),
             "fp64_iters": int(last.fp64_iters),
             "flag": int(last.flag),
             "err_true": last.err_true,
+            "err_recursive": last.err_recursive,
             "setup_ms": last.setup_ms,
             "matrix_setup_ms": create_ms,
         },

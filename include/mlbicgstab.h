@@ -99,6 +99,19 @@ typedef struct {
  * f_s = M^{-H} A^H q_s are those of Algorithm 7.1.  create() fails with
  * MLB_EINVAL if a (block) row has no stored diagonal entry or a singular one.
  * MLB_PRECOND_NONE (0) is M = I, Algorithm 4.1.
+ *
+ * transpose_free = 1 runs the iteration without A^H (an addition of this
+ * library; Section 4 names A^H-free algorithms but prints only their costs).
+ * The beta recurrence of step 2 of Algorithm 4.1 needs
+ * f_s^H g = (A^H q_s)^H g = q_s^H (A g): at every inner step the product
+ * v = A g of the vector entering that recurrence is formed first, the
+ * coefficients use q_s^H v, and w_k = v + sum_s beta_s w_s is recombined from
+ * this cycle's w columns instead of multiplied again.  Same matvec and dot
+ * counts as Algorithm 7.1, (n-1)/2 more saxpys per iteration, no A^H and no
+ * f_1..f_{n-1} stored: Table 4.2's costs (2n + 2 + 2/n saxpys, (3n + 5) N
+ * storage).  The recursive residual can drift further from b - A x than with
+ * A^H (Section 5.1 reports this for the second algorithm); err_true reports
+ * the true residual.  mlbicgstab_solve_batch refuses such handles.
  */
 typedef struct {
   int32_t n;
@@ -111,6 +124,7 @@ typedef struct {
   int32_t record_iterates;
   void* iterates;           /* device, N x record_iterates, or NULL            */
   int32_t precond;          /* MLB_PRECOND_NONE or MLB_PRECOND_JACOBI          */
+  int32_t transpose_free;   /* 0: Algorithm 7.1 with A^H; 1: without A^H       */
 } mlb_options;
 
 typedef struct {
@@ -129,6 +143,8 @@ typedef struct {
  * transpose A^H (Algorithm 4.1, step 2 needs A^H q_s) as an explicit device
  * copy, allocates the Krylov workspace ((4n+4) N values plus O(n^2)
  * scalars, Table 4.3) and, for MLB_PREC_FP32_IR, fp32 copies of A and A^H.
+ * With transpose_free neither A^H nor f_1..f_{n-1} is made ((3n+5) N values,
+ * Table 4.2).
  * hip_stream: a hipStream_t (NULL = default stream).  On success *out holds
  * the handle; on error *out is NULL.
  */
@@ -216,9 +232,12 @@ const char* mlbicgstab_last_error(void);
 int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* ms_per_launch);
 
 enum {
-  MLB_KERNEL_SPMV_STEP = 0,   /* SpMV + combination + multi-dot of an inner step */
+  MLB_KERNEL_SPMV_STEP = 0,   /* SpMV + multi-dot of a step (every SpMV of a cycle
+                                 but the one of the minimisation step)           */
   MLB_KERNEL_ALPHA_STEP = 1,  /* x, r update + norm + multi-dot                   */
-  MLB_KERNEL_COMBINE = 2      /* beta~ combination + F multi-dot                  */
+  MLB_KERNEL_COMBINE = 2,     /* beta~ combination + F multi-dot                  */
+  MLB_KERNEL_RECOMBINE = 3    /* g_k = g + sum beta_s g_s (transpose_free: also
+                                 w_k and its multi-dot)                          */
 };
 
 /*
@@ -228,7 +247,8 @@ enum {
  *
  * A server owns max_inflight workers, each with its own HIP stream, and (when
  * small_n_max >= 0) two batchers with a stream each.  Small requests (CSR,
- * fp64, no preconditioner, no iterate record, N <= small_n_max) wait for the
+ * fp64, no preconditioner, no iterate record, not transpose_free,
+ * N <= small_n_max) wait for the
  * batchers; a free batcher takes every waiting small request that fits (at
  * most 256) and solves them in one launch of mlbicgstab_solve_batch's kernel.
  * Other requests wait for the workers, which run create, solve and destroy

@@ -292,6 +292,7 @@ struct Engine {
   long long ldq = 0;
 
   bool own_flag = true;
+  bool tf = false;   // transpose-free inner steps: no A^H, no F (set before init)
 
   // ext_flag: a pinned, host-mapped int the caller owns (serving workers reuse one
   // per worker); NULL = allocate one.
@@ -305,7 +306,7 @@ struct Engine {
     const size_t Nn = (size_t)N * n_alloc;
     G = al.get<V>(Nn);
     W = al.get<V>(Nn);
-    F = al.get<V>((size_t)N * std::max(n_alloc - 1, 1));
+    F = tf ? nullptr : al.get<V>((size_t)N * std::max(n_alloc - 1, 1));
     r = al.get<V>(N);
     gt = al.get<V>(N);
     z = al.get<V>(N);
@@ -350,8 +351,8 @@ struct Engine {
       if (e) (void)hipEventDestroy(e);
   }
 
-  static size_t bytes(int N, int n) {
-    return sizeof(V) * ((size_t)N * (2 * n + std::max(n - 1, 1) + 3)) + sizeof(State<Sc>) +
+  static size_t bytes(int N, int n, bool tf) {
+    return sizeof(V) * ((size_t)N * (2 * n + (tf ? 0 : std::max(n - 1, 1)) + 3)) + sizeof(State<Sc>) +
            sizeof(Sc) * (size_t)(MAX_PARTIAL_ROWS + PSUM_GRID) * (NMAX + 1);
   }
 
@@ -425,7 +426,41 @@ struct Engine {
   // G_i = g + sum_{s<i} beta_s G_s (beta from the last PH_COMBINE)
   void gcomb(const V* gin, int i, int flags = 0) {
     flags |= force_flags;
-    k_gcomb<V, Sc><<<grid_vec, BLOCK, 0, s>>>(st, N, gin, G, N, i, G + (size_t)i * N, flags);
+    const Timed tm = timed(MLB_KERNEL_RECOMBINE);
+    MLB_LAUNCH((k_gcomb<V, Sc>), grid_vec, s, tm, st, N, gin, (const V*)G, (long long)N, i, G + (size_t)i * N, flags);
+  }
+  // Transpose-free step i: v = A g -> W_i with q_s^H v, s < i, and the beta
+  // recurrence (f_s^H g = q_s^H v).
+  void spmv_h(const V* gin, int i, int j) {
+    SpmvArgs<V> a{};
+    a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
+    a.xin = gin; a.out1 = W + (size_t)i * N; a.out2 = nullptr;
+    a.Q = Q; a.ldq = ldq; a.d0 = 0; a.nd = i;
+    const int flags = force_flags;
+    const Timed tm = timed(MLB_KERNEL_SPMV_STEP);
+    switch (nb) {
+      case 4: launch_spmv_nd<V, Sc, SM_STEP, 4>(A, grid_spmv, s, st, part, a, PH_COMBINE, i, j, n, flags, tm); break;
+      case 8: launch_spmv_nd<V, Sc, SM_STEP, 8>(A, grid_spmv, s, st, part, a, PH_COMBINE, i, j, n, flags, tm); break;
+      case 16: launch_spmv_nd<V, Sc, SM_STEP, 16>(A, grid_spmv, s, st, part, a, PH_COMBINE, i, j, n, flags, tm); break;
+      default: launch_spmv_nd<V, Sc, SM_STEP, 32>(A, grid_spmv, s, st, part, a, PH_COMBINE, i, j, n, flags, tm); break;
+    }
+    scalar(grid_spmv, nb, i, PH_COMBINE, i, j);
+  }
+  // Transpose-free step i: g_k -> G_i, w_k = v + sum beta_s W_s -> W_i, S column i,
+  // c_i and the next alpha.
+  void gwcomb(const V* gin, int i) {
+    const int flags = force_flags;
+    const Timed tm = timed(MLB_KERNEL_RECOMBINE);
+#define MLB_GW(B) \
+  MLB_LAUNCH((k_gwcomb<V, Sc, B>), grid_vec, s, tm, st, part, N, gin, G, W, (long long)N, i, Q, ldq, n, flags)
+    switch (nb) {
+      case 4: MLB_GW(4); break;
+      case 8: MLB_GW(8); break;
+      case 16: MLB_GW(16); break;
+      default: MLB_GW(32); break;
+    }
+#undef MLB_GW
+    scalar(grid_vec, nb, n - i, PH_SPMV_STEP, i, 0);
   }
   // w_i = A G_i ; S[s][i] = q_s^H w_i, s = i..n-1.  With gin != G_i the input is
   // also copied to G_i (cycle close and set-up, where g_k = g).
@@ -497,6 +532,18 @@ struct Engine {
     for (int i = 1; i < n; ++i) {
       // x_{jn+i} = x + alpha g ; r_{jn+i} = r - alpha w ; e = q_{i+1}^H r (and q_s^H r, s > i, when j >= 1)
       alpha(x, i - 1, i, j >= 1 ? n - i : 1, PH_INNER, i, j, xrec, K);
+      if (tf) {
+        // g = z_w - g/omega (j >= 1) or r (j = 0); v = A g and the beta recurrence from
+        // q_s^H v; g_{jn+i}, w_{jn+i} = v + sum beta_s w_s, c and S column i
+        const V* g0 = r;
+        if (j >= 1) {
+          combine(i, n, 0, i, j, gt);
+          g0 = gt;
+        }
+        spmv_h(g0, i, j);
+        gwcomb(g0, i);
+        continue;
+      }
       // g = z_w - g/omega from the previous cycle's columns (j >= 1), or g = r (j = 0); f_s^H g, s < i
       if (j >= 1) combine(i, n, i, i, j, gt);
       else combine(i, i, i, i, j, gt);
@@ -532,8 +579,9 @@ struct Engine {
     k_init_state<Sc><<<1, 1, 0, s>>>(st, tol, maxit, kappa, host_done_dev, stag_window);
     // r_0 = b - A x_0, ||b||, e_0 = q_1^H r_0, early exit
     spmv_resid(A, x, b, r, Q, PH_SETUP);
-    // f_s = A^H q_s, s = 1..n-1
-    for (int c = 0; c + 1 < n; ++c) spmv_plain(AH, Q + (size_t)c * ldq, F + (size_t)c * N);
+    // f_s = A^H q_s, s = 1..n-1 (not used by the transpose-free steps)
+    if (!tf)
+      for (int c = 0; c + 1 < n; ++c) spmv_plain(AH, Q + (size_t)c * ldq, F + (size_t)c * N);
     // g_0 = r_0, w_0 = A g_0, c_0 (and S column 0), alpha_1 = e_0 / c_0
     spmv_step(r, 0);
     HIP_TRY(hipEventRecord(t1, s));
@@ -632,6 +680,7 @@ static void check_options(const mlb_options* opt) {
     throw Error{MLB_EINVAL, "precision must be MLB_PREC_FP64 or MLB_PREC_FP32_IR"};
   if (opt->precond != MLB_PRECOND_NONE && opt->precond != MLB_PRECOND_JACOBI)
     throw Error{MLB_EINVAL, "precond must be MLB_PRECOND_NONE or MLB_PRECOND_JACOBI"};
+  if (opt->transpose_free != 0 && opt->transpose_free != 1) throw Error{MLB_EINVAL, "transpose_free must be 0 or 1"};
   if (opt->record_iterates < 0) throw Error{MLB_EINVAL, "record_iterates must be >= 0"};
   if (opt->record_iterates > 0) {
     if (!opt->iterates) throw Error{MLB_EINVAL, "record_iterates > 0 needs an iterates buffer"};
@@ -706,7 +755,9 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
     if (hb & 2) throw Error{MLB_EINVAL, "Jacobi preconditioner: a diagonal (block) is singular"};
     A.val = scaled;
   }
-  Mat<V64> AH = build_transpose(A, h->al, h->s);
+  const bool tf = h->opt.transpose_free != 0;
+  const Mat<V64> AH = tf ? Mat<V64>{} : build_transpose(A, h->al, h->s);
+  im.e64.tf = tf;
   im.e64.init(A, AH, h->opt.n, h->s, h->al, h->ext_flags);
   im.r64 = h->al.get<V64>(h->N);
   if (h->opt.precision == MLB_PREC_FP32_IR) {
@@ -721,16 +772,17 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
     AH32.rp = AH.rp;
     AH32.ci = AH.ci;
     V32* v = h->al.get<V32>((size_t)A.nnz * bs);
-    V32* vt = h->al.get<V32>((size_t)A.nnz * bs);
+    V32* vt = tf ? nullptr : h->al.get<V32>((size_t)A.nnz * bs);
     const long long m = (long long)A.nnz * bs;
     if (m > 0) {
       k_narrow<V32, V64><<<grid_for(m, 4096), BLOCK, 0, h->s>>>(v, A.val, m);
-      k_narrow<V32, V64><<<grid_for(m, 4096), BLOCK, 0, h->s>>>(vt, AH.val, m);
+      if (!tf) k_narrow<V32, V64><<<grid_for(m, 4096), BLOCK, 0, h->s>>>(vt, AH.val, m);
     }
     A32.val = v;
     AH32.val = vt;
     A32.lpr = A.lpr;
     AH32.lpr = AH.lpr;
+    im.e32.tf = tf;
     im.e32.init(A32, AH32, h->opt.n, h->s, h->al, h->ext_flags ? h->ext_flags + 1 : nullptr);
     im.has32 = true;
     im.b32 = h->al.get<V32>(h->N);
@@ -1012,6 +1064,7 @@ static void check_batchable(const mlb_solver* h) {
   if (h->format != MLB_CSR) throw Error{MLB_EUNSUPPORTED, "batched solves take CSR matrices"};
   if (h->opt.precision != MLB_PREC_FP64) throw Error{MLB_EUNSUPPORTED, "batched solves run in fp64"};
   if (h->opt.precond != MLB_PRECOND_NONE) throw Error{MLB_EUNSUPPORTED, "batched solves take no preconditioner"};
+  if (h->opt.transpose_free) throw Error{MLB_EUNSUPPORTED, "batched solves use A^H (no transpose_free)"};
   if (h->N > MLB_BATCH_MAX_N) throw Error{MLB_EUNSUPPORTED, "batched solves take at most MLB_BATCH_MAX_N rows"};
 }
 
@@ -1138,14 +1191,15 @@ int mlbicgstab_workspace_size(const mlb_matrix* A, const mlb_options* opt, size_
     const int bs = A->format == MLB_BSR3 ? 9 : 1;
     const bool c = A->dtype == MLB_C128;
     const size_t sv = c ? 16 : 8;
-    size_t t = (size_t)(nbr + 1) * 4 + (size_t)A->nnz * 4 + (size_t)A->nnz * bs * sv;   // A^H
-    t += c ? Engine<cplx<double>>::bytes(N, opt->n) : Engine<double>::bytes(N, opt->n);
+    const bool tf = opt->transpose_free != 0;
+    size_t t = tf ? 0 : (size_t)(nbr + 1) * 4 + (size_t)A->nnz * 4 + (size_t)A->nnz * bs * sv;   // A^H
+    t += c ? Engine<cplx<double>>::bytes(N, opt->n, tf) : Engine<double>::bytes(N, opt->n, tf);
     t += (size_t)N * sv;                                                                   // r64
     if (opt->precond == MLB_PRECOND_JACOBI)                                                // M, M^{-1}, A M^{-1}
       t += (size_t)nbr * bs * 2 * sv + (size_t)A->nnz * bs * sv;
     if (opt->precision == MLB_PREC_FP32_IR) {
-      t += (size_t)A->nnz * bs * sv;                                                       // fp32 A, A^H values
-      t += c ? Engine<cplx<float>>::bytes(N, opt->n) : Engine<float>::bytes(N, opt->n);
+      t += (size_t)A->nnz * bs * (tf ? sv / 2 : sv);                                       // fp32 A (and A^H) values
+      t += c ? Engine<cplx<float>>::bytes(N, opt->n, tf) : Engine<float>::bytes(N, opt->n, tf);
       t += (size_t)N * (2 + opt->n) * (sv / 2);
     }
     *bytes = t;
@@ -1257,7 +1311,7 @@ int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* m
   return guarded([&]() -> int {
     if (!h || !ms_per_launch) throw Error{MLB_EINVAL, "handle and ms_per_launch must be non-NULL"};
     if (!h->solved) throw Error{MLB_EINVAL, "time_kernel needs a prior solve"};
-    if (kernel < MLB_KERNEL_SPMV_STEP || kernel > MLB_KERNEL_COMBINE) throw Error{MLB_EINVAL, "unknown kernel"};
+    if (kernel < MLB_KERNEL_SPMV_STEP || kernel > MLB_KERNEL_RECOMBINE) throw Error{MLB_EINVAL, "unknown kernel"};
     if (reps < 1) throw Error{MLB_EINVAL, "reps must be >= 1"};
     const bool ir = h->opt.precision == MLB_PREC_FP32_IR;
     if (h->real)
@@ -1575,7 +1629,7 @@ int mlb_server_submit(mlb_server_handle S, const mlb_matrix* A, const mlb_option
       r->t_submit = now_s();
       S->table[r->ticket] = r;
       r->small = A->format == MLB_CSR && opt->precision == MLB_PREC_FP64 && opt->precond == MLB_PRECOND_NONE &&
-                 opt->record_iterates == 0 && A->nrows <= S->small_n_max;
+                 opt->record_iterates == 0 && !opt->transpose_free && A->nrows <= S->small_n_max;
       (r->small ? S->small_queue : S->queue).push_back(r);
       *ticket = r->ticket;
     }

@@ -22,6 +22,12 @@
 // forms g_k = g + sum b_s g_s, and the SpMV pass forms w_k = A g_k from the
 // stored g_k (a fresh product: recombining old w columns instead would save
 // the pass but lets w_k drift from A g_k and costs attainable accuracy).
+//
+// Transpose-free variant: f_s^H g = q_s^H (A g), so the SpMV pass forms
+// v = A g before the beta recurrence and reduces q_s^H v (s < i) for it; one
+// pass (k_gwcomb) then forms g_k = g + sum b_s g_s and w_k = v + sum b_s w_s
+// (the recombination, the price of having no A^H) and reduces q_s^H w_k,
+// s >= i, the S column and c of step i.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -494,6 +500,55 @@ __global__ __launch_bounds__(BLOCK) void k_gcomb(const State<Sc>* st, int N, con
     for (; s < nb; ++s) v = axpy(v, bco[s], Gb[row + s * ldg]);
     gout[row] = v;
   }
+}
+
+// Transpose-free step i: g_k = g + sum_{s<i} beta_s G_s -> G_i and
+// w_k = v + sum_{s<i} beta_s W_s -> W_i, where v = A g was stored in W_i by the
+// SpMV pass; sums: q_s^H w_k, s in [i, n) (the S column of step i).  beta is
+// staged in LDS; every row of W_i is read before the same thread writes it.
+template <class V, class Sc, int ND>
+__global__ __launch_bounds__(BLOCK) void k_gwcomb(State<Sc>* st, Sc* partial, int N, const V* __restrict__ g,
+                                                  V* G, V* W, long long ld, int i, const V* __restrict__ Q,
+                                                  long long ldq, int n, int flags) {
+  if (!(flags & F_IGNORE_DONE) && st->done) return;
+  __shared__ V bco[NMAX];
+  if (threadIdx.x < i) bco[threadIdx.x] = convert<V>(st->beta[threadIdx.x]);
+  __syncthreads();
+  V acc[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = zero<V>();
+  const int nd = n - i;
+  V* Gi = G + i * ld;
+  V* Wi = W + i * ld;
+  for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
+    V gv = g[row];
+    V wv = Wi[row];
+    int s = 0;
+    for (; s + 4 <= i; s += 4) {   // loads of 4 column pairs issued together, same order of updates
+      V ga[4], wa[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ga[u] = G[row + (s + u) * ld];
+        wa[u] = W[row + (s + u) * ld];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        gv = axpy(gv, bco[s + u], ga[u]);
+        wv = axpy(wv, bco[s + u], wa[u]);
+      }
+    }
+    for (; s < i; ++s) {
+      gv = axpy(gv, bco[s], G[row + s * ld]);
+      wv = axpy(wv, bco[s], W[row + s * ld]);
+    }
+    Gi[row] = gv;
+    Wi[row] = wv;
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+      if (d < nd) cdot_acc(acc[d], Q[row + (long long)(i + d) * ldq], wv);
+  }
+  if (flags & F_SKIP_SCALAR) return;
+  block_partials<ND>(acc, nd, partial);
 }
 
 // x += omega u ; r = u - omega z (u held in r) ; sums: ||r||^2, q_s^H r, s < nd.

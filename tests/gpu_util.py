@@ -31,7 +31,7 @@ def block_jacobi(A):
     return (lambda v: v / d, lambda v: v / np.conj(d))
 
 
-def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None, precond=0):
+def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None, precond=0, transpose_free=False):
     """Solve problem p on the GPU; returns (result, x, iterates or None)."""
     from paper_1106_3678_amd import binding
 
@@ -45,7 +45,8 @@ def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None, pre
     K = min(record, mi)
     it = torch.zeros((K, p.N), dtype=dt, device="cuda") if K else None
     s = binding.Solver(dA, p.n, tol=p.tol, maxit=mi, kappa=p.kappa if kappa is None else kappa,
-                       precision=precision, inner_tol=inner_tol, record_iterates=K, iterates=it, precond=precond)
+                       precision=precision, inner_tol=inner_tol, record_iterates=K, iterates=it, precond=precond,
+                       transpose_free=transpose_free)
     try:
         res = s.solve(b, x, Q)
         torch.cuda.synchronize()
@@ -56,11 +57,11 @@ def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None, pre
     return res, xs, its
 
 
-def run_oracle(p, record=0, maxit=None, kappa=None, precond=0, summation="blas"):
+def run_oracle(p, record=0, maxit=None, kappa=None, precond=0, summation="blas", transpose_free=False):
     pre = block_jacobi(p.A) if precond else None
     return oracle.mlbicgstabt(p.A, p.b, p.Q, x0=p.x0, tol=p.tol, maxit=p.maxit if maxit is None else maxit,
                               kappa=p.kappa if kappa is None else kappa, record_x=record, precond=pre,
-                              summation=summation)
+                              summation=summation, transpose_free=transpose_free)
 
 
 def rel(a, b):
@@ -73,7 +74,7 @@ def iters_close(a, b):
     return abs(a - b) <= max(1, int(0.05 * max(a, b)))
 
 
-def oracle_spread(p, base, K=20, precond=0):
+def oracle_spread(p, base, K=20, precond=0, transpose_free=False):
     """How far the oracle itself moves under rounding-level changes.
 
     Re-runs the oracle (a) with its inner products summed in other orders
@@ -88,7 +89,8 @@ def oracle_spread(p, base, K=20, precond=0):
     variants = [("exact", p.b), ("reversed", p.b), ("blas", p.b * (1 + 1e-15 * g.standard_normal(p.N)))]
     for summation, b in variants:
         o2 = oracle.mlbicgstabt(p.A, b, p.Q, x0=p.x0, tol=p.tol, maxit=p.maxit, kappa=p.kappa, record_x=K,
-                                summation=summation, precond=block_jacobi(p.A) if precond else None)
+                                summation=summation, precond=block_jacobi(p.A) if precond else None,
+                                transpose_free=transpose_free)
         kk = min(K, o2.iter, base.iter)
         for k in range(kk):
             it_spread = max(it_spread, rel(o2.x_history[k], base.x_history[k]))

@@ -50,7 +50,7 @@ def _desc(binding, **kw):
 
 def _opt(binding, **kw):
     o = dict(n=4, tol=1e-10, maxit=100, kappa=0.0, precision=0, inner_tol=0.0, max_outer=0, record_iterates=0,
-             iterates=None, precond=0)
+             iterates=None, precond=0, transpose_free=0)
     o.update(kw)
     return binding.mlb_options(**o)
 
@@ -60,7 +60,7 @@ def _opt(binding, **kw):
     dict(m=dict(nnz=-1)), dict(m=dict(row_ptr=None)),
     dict(o=dict(n=0)), dict(o=dict(tol=0.0)), dict(o=dict(tol=float("nan"))), dict(o=dict(maxit=0)),
     dict(o=dict(kappa=-1.0)), dict(o=dict(precision=5)), dict(o=dict(record_iterates=3)),
-    dict(o=dict(precond=7)),
+    dict(o=dict(precond=7)), dict(o=dict(transpose_free=2)),
 ])
 def test_create_rejects_bad_arguments(binding, bad):
     A = _desc(binding, **bad.get("m", {}))
@@ -104,6 +104,27 @@ def test_workspace_size_model(binding):
     assert s2 > s1 and s3 > 1.9 * s1
     # 3 vectors (G, W, F) per extra shadow vector, 8 bytes each
     assert abs((s2 - s1) - 4 * 3 * 30000 * 8) < 1024
+
+
+@pytest.mark.parametrize("n", [1, 4, 16])
+@pytest.mark.parametrize("dtype,fmt", [(0, 0), (1, 0), (0, 1)])
+def test_workspace_size_transpose_free(binding, n, dtype, fmt):
+    """Without A^H the footprint drops by A^H (row pointers, indices, values) and by the
+    n - 1 columns of F ((3n + 5) N instead of (4n + 4) N, Tables 4.2 and 4.3)."""
+    N, nnz = 30000, 150000 // (9 if fmt else 1)
+    sv = 16 if dtype else 8
+    bs = 9 if fmt else 1
+    nbr = N // 3 if fmt else N
+    desc = _desc(binding, nrows=N, nnz=nnz, dtype=dtype, format=fmt)
+    full = binding.mlbicgstab_workspace_size(desc, _opt(binding, n=n))
+    tf = binding.mlbicgstab_workspace_size(desc, _opt(binding, n=n, transpose_free=1))
+    ah = (nbr + 1) * 4 + nnz * 4 + nnz * bs * sv
+    f = max(n - 1, 1) * N * sv
+    assert full - tf == ah + f
+    # the fp32 refinement mode also drops the fp32 copy of A^H's values and the fp32 F
+    full32 = binding.mlbicgstab_workspace_size(desc, _opt(binding, n=n, precision=1))
+    tf32 = binding.mlbicgstab_workspace_size(desc, _opt(binding, n=n, precision=1, transpose_free=1))
+    assert full32 - tf32 == ah + f + nnz * bs * sv // 2 + f // 2
 
 
 def test_server_rejects_bad_options(binding):
