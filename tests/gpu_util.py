@@ -74,19 +74,22 @@ def iters_close(a, b):
     return abs(a - b) <= max(1, int(0.05 * max(a, b)))
 
 
-def oracle_spread(p, base, K=20, precond=0, transpose_free=False):
+def oracle_spread(p, base, K=20, precond=0, transpose_free=False, n_perturb=1):
     """How far the oracle itself moves under rounding-level changes.
 
     Re-runs the oracle (a) with its inner products summed in other orders
     (correctly rounded, reversed) and (b) with b scaled entrywise by
-    (1 + 1e-15 xi), xi ~ N(0, 1).  Returns (max relative iterate change over
-    k <= K, max |iteration count change|, max true residual, max relative change
-    of the final x).  Two correct fp64 implementations that only differ in
-    rounding order cannot be expected to agree better than this.
+    (1 + 1e-15 xi), xi ~ N(0, 1), n_perturb times (the k-th perturbed run sums
+    in the k-th of the orders blas, exact, reversed).  Returns (max relative
+    iterate change over k <= K, max |iteration count change|, max true residual,
+    max relative change of the final x).  Two correct fp64 implementations that
+    only differ in rounding order cannot be expected to agree better than this.
     """
     it_spread, n_spread, true_max, x_spread = 0.0, 0, oracle.true_error(p.A, base.x, p.b), 0.0
     g = np.random.default_rng(1)
-    variants = [("exact", p.b), ("reversed", p.b), ("blas", p.b * (1 + 1e-15 * g.standard_normal(p.N)))]
+    variants = [("exact", p.b), ("reversed", p.b)]
+    for k in range(n_perturb):
+        variants.append((("blas", "exact", "reversed")[k % 3], p.b * (1 + 1e-15 * g.standard_normal(p.N))))
     for summation, b in variants:
         o2 = oracle.mlbicgstabt(p.A, b, p.Q, x0=p.x0, tol=p.tol, maxit=p.maxit, kappa=p.kappa, record_x=K,
                                 summation=summation, precond=block_jacobi(p.A) if precond else None,

@@ -4,7 +4,11 @@ transpose-free variant, element by element.
 Bars as for Algorithm 7.1 (same flag, iteration counts within 5%, x_1..x_20 within
 1e-8 relative, true residual below tol, x within 1e-6 of the oracle's x).  On the
 ill-conditioned block system the recursive residual drifts from the true one on
-both sides, so there each bar is widened to the oracle's own rounding-level spread.
+both sides (the drift Section 5.1 reports for the A^H-free second algorithm), so
+there each bar is widened to the oracle's own rounding-level spread.  That spread
+is sampled over 24 perturbed runs: the drifted final true residual is chaotic under
+rounding (2e-11 to 4.3e-9 across 24 oracle runs of the 8x10x6 block-Jacobi case),
+so a sample of three understates it.
 Also: bitwise reruns, finite termination, the fp32 refinement and preconditioned
 modes, sequences and serving, the kernel timer, refusal by the batch kernel, and
 the 128^3 workload's first iterates in the benchmark's launch configuration.
@@ -31,7 +35,7 @@ def check_tf(p, K=20, x_tol=1e-6, sensitive=False, precond=0):
     o = run_oracle(p, record=K, precond=precond, transpose_free=True)
     it_tol, n_tol, res_tol = 1e-8, max(1, int(0.05 * o.iter)), p.tol + 1e-12
     if sensitive:
-        s_it, s_n, s_true, s_x = oracle_spread(p, o, K, precond=precond, transpose_free=True)
+        s_it, s_n, s_true, s_x = oracle_spread(p, o, K, precond=precond, transpose_free=True, n_perturb=24)
         it_tol = max(it_tol, 10 * s_it)
         n_tol = max(n_tol, 2 * s_n)
         res_tol = max(res_tol, 3 * s_true)
