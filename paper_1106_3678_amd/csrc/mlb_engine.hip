@@ -383,10 +383,10 @@ struct Engine {
   template <int STRIDE>
   void scalar_t(int nblocks, int nsum, int phase, int i, int j) {
     if (two_stage<Sc, STRIDE>() && nblocks > PSUM_GRID) {
-      k_psum<Sc, STRIDE><<<PSUM_GRID, BLOCK, 0, s>>>(st, part, nblocks, nsum, part2);
-      k_scalar<Sc, STRIDE><<<1, BLOCK, 0, s>>>(st, part2, PSUM_GRID, nsum, phase, i, j, n);
+      k_psum<Sc, STRIDE><<<PSUM_GRID, BLOCK, 0, s>>>(part, nblocks, nsum, part2);
+      k_scalar<Sc, STRIDE><<<1, sblock<Sc, STRIDE>(), 0, s>>>(st, part2, PSUM_GRID, nsum, phase, i, j, n);
     } else {
-      k_scalar<Sc, STRIDE><<<1, BLOCK, 0, s>>>(st, part, nblocks, nsum, phase, i, j, n);
+      k_scalar<Sc, STRIDE><<<1, sblock<Sc, STRIDE>(), 0, s>>>(st, part, nblocks, nsum, phase, i, j, n);
     }
   }
   void scalar(int nblocks, int stride, int nsum, int phase, int i, int j) {

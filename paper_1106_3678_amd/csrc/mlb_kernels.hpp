@@ -42,6 +42,16 @@ constexpr int NMAX = 32;        // largest n
 constexpr int MAX_PARTIAL_ROWS = 2048;   // most workgroups of a reducing pass
 constexpr int PSUM_GRID = 64;            // first-stage workgroups for long partial rows
 constexpr int BLOCK = 256;      // threads per workgroup (4 waves of 64)
+// Complex partial rows longer than 64 bytes are summed in two stages (k_psum
+// first): the one-workgroup stage does not keep enough of their 16-byte loads
+// in flight.
+template <class Sc, int STRIDE>
+constexpr bool wide_rows() { return sizeof(Sc) > 8 && STRIDE * sizeof(Sc) > 64; }
+// Threads of the one-workgroup recurrence kernel (k_scalar) for partial rows of
+// STRIDE entries: 1024 for the longer real rows, which keeps more of a long
+// table's loads in flight.
+template <class Sc, int STRIDE>
+constexpr int sblock() { return STRIDE <= 5 || wide_rows<Sc, STRIDE>() ? 256 : 1024; }
 constexpr int WAVE = 64;
 
 // Kernel flags
@@ -316,83 +326,124 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
 }
 
 // Sums rows [r0, r1) of a pass's partials (row length STRIDE) into
-// sums[0..nsum) in LDS, in a fixed order.  Thread (g, d) of the workgroup
-// (d = t % STRIDE, g = t / STRIDE, G = BLOCK / STRIDE groups) adds entry d of
-// rows g, g + G, g + 2G, ... in that order, with 8 loads in flight (adjacent
-// threads read adjacent words); the G group sums of each entry are then added
-// in group order.  MAXR is the most rows a call sees: each thread then loads
-// all its rows in one batch.  Ends with a barrier; every thread must call it.
-template <class Sc, int STRIDE, int MAXR>
+// sums[0..nsum) in LDS, in a fixed order, with NT threads.  Thread (g, d)
+// (d = t % STRIDE, g = t / STRIDE, G = NT / STRIDE groups) adds entry d of
+// rows g, g + G, g + 2G, ... in that order; the rows are loaded in batches of
+// SUM_BATCH, all loads of a batch issued before its adds (adjacent threads read
+// adjacent words).  The G group sums of each entry are then added in group
+// order; beyond 64 groups in a fixed two-level order instead (32 runs of
+// consecutive groups, then the run sums), which keeps the dependent chain
+// short.  Ends with a barrier; every thread must call it.
+constexpr int SUM_BATCH = 16;
+template <class Sc, int STRIDE, int NT>
 __device__ void sum_rows(const Sc* __restrict__ partial, int r0, int r1, int nsum, Sc* sums) {
-  constexpr int G = BLOCK / STRIDE;
-  constexpr int U = (MAXR + G - 1) / G;   // rows loaded together
+  constexpr int G = NT / STRIDE;
   __shared__ Sc red[G][STRIDE];
   const int t = threadIdx.x, d = t % STRIDE, g = t / STRIDE;
   const int nrows = r1 - r0;
   if (g < G && d < nsum) {
     const Sc* base = partial + (size_t)r0 * STRIDE + d;
     Sc acc = zero<Sc>();
-    for (int k0 = g; k0 < nrows; k0 += U * G) {
-      Sc v[U];
+    for (int k0 = g; k0 < nrows; k0 += SUM_BATCH * G) {
+      Sc v[SUM_BATCH];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < SUM_BATCH; ++u) {
         const int r = k0 + u * G;
         v[u] = base[(size_t)(r < nrows ? r : 0) * STRIDE];   // row 0 of the range re-read, unused
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < SUM_BATCH; ++u)
         if (k0 + u * G < nrows) add_(acc, v[u]);
     }
     red[g][d] = acc;
   }
   __syncthreads();
-  if (t < nsum) {
-    Sc v = red[0][t];
-    for (int q = 1; q < G; ++q) add_(v, red[q][t]);
-    sums[t] = v;
+  if constexpr (G <= 64) {
+    if (t < nsum) {
+      Sc v = red[0][t];
+      for (int q = 1; q < G; ++q) add_(v, red[q][t]);
+      sums[t] = v;
+    }
+  } else {
+    constexpr int H = 32;
+    __shared__ Sc red2[H][STRIDE];
+    if (g < H && d < nsum) {
+      const int q0 = g * G / H, q1 = (g + 1) * G / H;
+      Sc v = red[q0][d];
+      for (int q = q0 + 1; q < q1; ++q) add_(v, red[q][d]);
+      red2[g][d] = v;
+    }
+    __syncthreads();
+    if (t < nsum) {
+      Sc v = red2[0][t];
+      for (int q = 1; q < H; ++q) add_(v, red2[q][t]);
+      sums[t] = v;
+    }
   }
   __syncthreads();
 }
 
-// Partial rows longer than 64 bytes (many shadow vectors, complex) are summed
-// in two stages: PSUM_GRID workgroups first.
+// Partial tables that would take the one-workgroup stage more than three load
+// batches per thread (long rows: many shadow vectors), and wide complex rows,
+// are summed in two stages, PSUM_GRID workgroups first (the extra launch costs
+// more than a third batch).
 template <class Sc, int STRIDE>
-constexpr bool two_stage() { return STRIDE * sizeof(Sc) > 64; }
+constexpr bool two_stage() {
+  constexpr int G = sblock<Sc, STRIDE>() / STRIDE;
+  return wide_rows<Sc, STRIDE>() || (MAX_PARTIAL_ROWS + G - 1) / G > 3 * SUM_BATCH;
+}
 
 // First stage: workgroup g sums the g-th contiguous share of the rows into row
-// g of `out`, so that the one-workgroup stage reads PSUM_GRID rows.
+// g of `out`, so that the one-workgroup stage reads PSUM_GRID rows.  It does not
+// test the done flag: after the end it sums stale partials into `out`, which
+// k_scalar then ignores, and it saves the flag's round trip before the loads.
 template <class Sc, int STRIDE>
-__global__ __launch_bounds__(BLOCK) void k_psum(const State<Sc>* st, const Sc* __restrict__ partial, int nblocks,
-                                                int nsum, Sc* __restrict__ out) {
-  if (st->done) return;
+__global__ __launch_bounds__(BLOCK) void k_psum(const Sc* __restrict__ partial, int nblocks, int nsum,
+                                                Sc* __restrict__ out) {
   __shared__ Sc sums[STRIDE];
   const int r0 = (int)((long long)nblocks * blockIdx.x / gridDim.x);
   const int r1 = (int)((long long)nblocks * (blockIdx.x + 1) / gridDim.x);
-  sum_rows<Sc, STRIDE, (MAX_PARTIAL_ROWS + PSUM_GRID - 1) / PSUM_GRID>(partial, r0, r1, nsum, sums);
+  sum_rows<Sc, STRIDE, BLOCK>(partial, r0, r1, nsum, sums);
   if (threadIdx.x < nsum) out[(size_t)blockIdx.x * STRIDE + threadIdx.x] = sums[threadIdx.x];
 }
 
-// One workgroup: sum the partials of the previous pass (or of k_psum) in a
-// fixed order and run the coefficient recurrence on one wave.  The state is
+// One workgroup of sblock<Sc, STRIDE>() threads: sum the partials of the previous pass (or of
+// k_psum) in a fixed order and run the coefficient recurrence on one wave.  The state is
 // staged in LDS for the recurrence (its loops read the n x n Gram matrix and
 // the coefficient lists entry by entry) and written back afterwards; rows
 // s >= n of the Gram matrix are never touched and stay out of both copies.
+// The state words (the done flag among them) and the partials are loaded in
+// one round trip: the flag is tested once both have arrived (after the end,
+// the partials read are stale and ignored; the buffer always holds nblocks
+// rows, so the reads stay in bounds).
 template <class Sc, int STRIDE>
-__global__ __launch_bounds__(BLOCK) void k_scalar(State<Sc>* st, const Sc* __restrict__ partial, int nblocks,
+__global__ __launch_bounds__((sblock<Sc, STRIDE>())) void k_scalar(State<Sc>* st, const Sc* __restrict__ partial, int nblocks,
                                                   int nsum, int phase, int i, int j, int n) {
-  if (st->done) return;
   static_assert(sizeof(State<Sc>) % 8 == 0 && offsetof(State<Sc>, S) % 8 == 0, "state is copied in 8-byte words");
+  constexpr int SB = sblock<Sc, STRIDE>();
+  constexpr int CW = (int)((sizeof(State<Sc>) / 8 + SB - 1) / SB);   // state words per thread, at most
   __shared__ State<Sc> ss;
   __shared__ Sc sums[STRIDE];
   const int nwords = (int)((offsetof(State<Sc>, S) + sizeof(Sc) * (size_t)n * NMAX) / 8);
   unsigned long long* gw = reinterpret_cast<unsigned long long*>(st);
   unsigned long long* lw = reinterpret_cast<unsigned long long*>(&ss);
-  for (int w = threadIdx.x; w < nwords; w += BLOCK) lw[w] = gw[w];
-  constexpr int MAXR = two_stage<Sc, STRIDE>() ? PSUM_GRID : MAX_PARTIAL_ROWS;
-  sum_rows<Sc, STRIDE, MAXR>(partial, 0, nblocks, nsum, sums);   // its barriers also order the copy
+  unsigned long long sw[CW];
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    const int w = threadIdx.x + c * SB;
+    sw[c] = w < nwords ? gw[w] : 0ull;
+  }
+  sum_rows<Sc, STRIDE, SB>(partial, 0, nblocks, nsum, sums);
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    const int w = threadIdx.x + c * SB;
+    if (w < nwords) lw[w] = sw[c];
+  }
+  __syncthreads();
+  if (ss.done) return;   // the same LDS word for every thread
   if (threadIdx.x < WAVE) scalar_program(&ss, sums, phase, i, j, n);
   __syncthreads();
-  for (int w = threadIdx.x; w < nwords; w += BLOCK) gw[w] = lw[w];
+  for (int w = threadIdx.x; w < nwords; w += SB) gw[w] = lw[w];
 }
 
 // ---------------------------------------------------------------- vector passes
