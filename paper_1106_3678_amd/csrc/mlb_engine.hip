@@ -342,6 +342,17 @@ struct Engine {
     }
     grid_vec = grid_for(N, std::min(MAX_GRID, 8 * cus));
     grid_spmv = grid_for(A.nbrows, std::min(MAX_GRID, occ * cus));
+    // The LDS-tile SpMV (BSR3, long CSR rows) takes 256-row tiles in rounds of
+    // the grid: the smallest grid with the same number of rounds gives every
+    // workgroup the same number of tiles, instead of a last round that is only
+    // partly filled while the rest waits (BSR3 step 186 -> 181 us at 60x220x85).
+    // The wave-local CSR kernel and the vector passes keep the full grid: for
+    // them the lower occupancy costs more than the imbalance.
+    if (!(A.format == MLB_CSR && A.lpr <= 8)) {
+      const long long tiles = (A.nbrows + BLOCK - 1) / BLOCK;
+      const long long rounds = (tiles + grid_spmv - 1) / grid_spmv;
+      grid_spmv = (int)std::max(1LL, (tiles + rounds - 1) / rounds);
+    }
   }
 
   void release() {
