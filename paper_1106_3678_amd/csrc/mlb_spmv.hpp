@@ -118,6 +118,9 @@ __device__ inline void csr_tile(const int* __restrict__ rp, const int* __restric
   }
 }
 
+// The block-row bounds of the wave's 64 block rows come from one row-pointer
+// load per lane (rows past the end read rp[nbrows]: empty rows) and lane
+// shuffles, so the passes start with their block loads.
 template <class V, int LPR>
 __device__ inline void bsr3_tile(const int* __restrict__ rp, const int* __restrict__ ci, const V* __restrict__ val,
                                  const V* __restrict__ xin, int nbrows, int brow0, V* ylds) {
@@ -125,13 +128,17 @@ __device__ inline void bsr3_tile(const int* __restrict__ rp, const int* __restri
   const int wbase = (threadIdx.x / WAVE) * WAVE;
   constexpr int RPP = WAVE / LPR;
   const int sub = lane % LPR, grp = lane / LPR;
+  const int rpl = rp[min(brow0 + wbase + lane, nbrows)];
+  const int rpn = rp[min(brow0 + wbase + WAVE, nbrows)];
 #pragma unroll 2
   for (int p = 0; p < LPR; ++p) {
     const int lb = wbase + p * RPP + grp;
-    const int brow = brow0 + lb;
+    const int idx = p * RPP + grp;   // block row - first block row of the wave
+    const int beg = __shfl(rpl, idx, WAVE);
+    const int e1 = __shfl(rpl, (idx + 1) & (WAVE - 1), WAVE);
+    const int end = idx == WAVE - 1 ? rpn : e1;
     V a0 = zero<V>(), a1 = zero<V>(), a2 = zero<V>();
-    if (brow < nbrows) {
-      const int beg = rp[brow], end = rp[brow + 1];
+    {
       for (int q = beg + sub; q < end; q += LPR) {
         const V* blk = val + (size_t)9 * q;
         const int c3 = 3 * ci[q];
