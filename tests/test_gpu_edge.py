@@ -2,7 +2,8 @@
 
 N = 1; more shadow vectors than unknowns (n > N); a right-hand side that is an eigenvector (exact
 after one step); an all-zero matrix with empty index arrays (breakdown at k = 0); a consistent
-singular system; an inconsistent singular system, which must not be reported as converged.
+singular system; an inconsistent singular system, which must not be reported as converged.  The
+multi-launch cases are also run without A^H (transpose_free) against the oracle's variant.
 """
 import numpy as np
 import pytest
@@ -80,3 +81,22 @@ def test_inconsistent_singular_is_not_converged():
     assert o.flag != 0
     for res, _ in (run_gpu(p)[:2], batch_solve(p)):
         assert res.flag != 0
+
+
+@pytest.mark.parametrize("p", CASES, ids=[c.name for c in CASES])
+def test_degenerate_transpose_free_matches_oracle(p):
+    """The same cases without A^H, against the oracle's transpose-free variant."""
+    o = oracle.mlbicgstabt(p.A, p.b, p.Q, tol=p.tol, maxit=p.maxit, transpose_free=True)
+    res, x = run_gpu(p, transpose_free=True)[:2]
+    print(f"{p.name} transpose-free: flag={res.flag} iter={res.iter} | oracle flag={o.flag} iter={o.iter}", flush=True)
+    assert res.flag == o.flag
+    assert res.iter == o.iter
+    if o.flag == 0:
+        assert rel(x, o.x) < 1e-10
+        assert np.linalg.norm(p.b - p.A @ x) <= 1e-9 * np.linalg.norm(p.b)
+
+
+def test_zero_matrix_transpose_free():
+    p = problem("zero", np.zeros((3, 3)), np.ones(3), np.ones((3, 2)))
+    res, x = run_gpu(p, transpose_free=True)[:2]
+    assert res.flag == -1 and res.iter == 0 and not x.any()
