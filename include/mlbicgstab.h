@@ -111,7 +111,7 @@ typedef struct {
  * f_1..f_{n-1} stored: Table 4.2's costs (2n + 2 + 2/n saxpys, (3n + 5) N
  * storage).  The recursive residual can drift further from b - A x than with
  * A^H (Section 5.1 reports this for the second algorithm); err_true reports
- * the true residual.  mlbicgstab_solve_batch refuses such handles.
+ * the true residual.
  */
 typedef struct {
   int32_t n;
@@ -170,7 +170,8 @@ int mlbicgstab_solve(mlb_handle h, const void* b, void* x, const void* Q, int64_
  * iteration is bound by launch latency rather than bandwidth).  Every h[k]
  * must come from mlbicgstab_create with a CSR matrix of at most
  * MLB_BATCH_MAX_N rows, MLB_PREC_FP64 and MLB_PRECOND_NONE (an iterate
- * record is kept as in a solve); all on the same stream and of the same value type (else
+ * record is kept as in a solve; transpose_free handles run the transpose-free
+ * steps); all on the same stream and of the same value type (else
  * MLB_EINVAL / MLB_EUNSUPPORTED, and nothing runs).  b[k], x[k], Q[k], ldq[k]
  * and res[k] (res may be NULL) as in mlbicgstab_solve.  A system's result
  * does not depend on the other systems of the batch.  Synchronises the
@@ -247,8 +248,7 @@ enum {
  *
  * A server owns max_inflight workers, each with its own HIP stream, and (when
  * small_n_max >= 0) two batchers with a stream each.  Small requests (CSR,
- * fp64, no preconditioner, no iterate record, not transpose_free,
- * N <= small_n_max) wait for the
+ * fp64, no preconditioner, no iterate record, N <= small_n_max) wait for the
  * batchers; a free batcher takes every waiting small request that fits (at
  * most 256) and solves them in one launch of mlbicgstab_solve_batch's kernel.
  * Other requests wait for the workers, which run create, solve and destroy

@@ -1075,7 +1075,6 @@ static void check_batchable(const mlb_solver* h) {
   if (h->format != MLB_CSR) throw Error{MLB_EUNSUPPORTED, "batched solves take CSR matrices"};
   if (h->opt.precision != MLB_PREC_FP64) throw Error{MLB_EUNSUPPORTED, "batched solves run in fp64"};
   if (h->opt.precond != MLB_PRECOND_NONE) throw Error{MLB_EUNSUPPORTED, "batched solves take no preconditioner"};
-  if (h->opt.transpose_free) throw Error{MLB_EUNSUPPORTED, "batched solves use A^H (no transpose_free)"};
   if (h->N > MLB_BATCH_MAX_N) throw Error{MLB_EUNSUPPORTED, "batched solves take at most MLB_BATCH_MAX_N rows"};
 }
 
@@ -1120,6 +1119,7 @@ static void batch_impl(mlb_solver* const* hs, int count, const void* const* b, v
     J.kappa = hs[k]->opt.kappa;
     J.maxit = hs[k]->opt.maxit;
     J.host_done = e.host_done_dev;
+    J.tf = e.tf ? 1 : 0;
     J.xrec = (V64*)hs[k]->opt.iterates;
     J.K = hs[k]->opt.record_iterates > 0 ? std::min<long long>(hs[k]->opt.record_iterates, hs[k]->opt.maxit) : 0;
     *(volatile int*)e.host_done = 0;
@@ -1640,7 +1640,7 @@ int mlb_server_submit(mlb_server_handle S, const mlb_matrix* A, const mlb_option
       r->t_submit = now_s();
       S->table[r->ticket] = r;
       r->small = A->format == MLB_CSR && opt->precision == MLB_PREC_FP64 && opt->precond == MLB_PRECOND_NONE &&
-                 opt->record_iterates == 0 && !opt->transpose_free && A->nrows <= S->small_n_max;
+                 opt->record_iterates == 0 && A->nrows <= S->small_n_max;
       (r->small ? S->small_queue : S->queue).push_back(r);
       *ticket = r->ticket;
     }

@@ -8,7 +8,9 @@
 // and the scalar state kept in LDS.  Systems are independent, so a result
 // does not depend on which other systems share the launch.  The vectors of a
 // system stay in the L2 / Infinity Cache at the sizes this path is used for.
-// Every workgroup ends after at most maxit / n + 2 cycles.
+// Every workgroup ends after at most maxit / n + 2 cycles.  A system may also
+// run the transpose-free steps (no A^H and no F; the same passes as the
+// multi-launch engine's spmv_h and k_gwcomb).
 #pragma once
 
 #include "mlb_kernels.hpp"
@@ -38,6 +40,7 @@ struct SmallJob {
   double tol = 0, kappa = 0;
   long long maxit = 0;
   int* host_done = nullptr;   // host-mapped done flag, or null
+  int tf = 0;                 // transpose-free inner steps (rpT, ciT, valT and F unused)
 };
 
 // Workgroup sums of acc[0..nd) into sums[0..nd) (LDS), fixed order: a tree
@@ -64,7 +67,7 @@ __device__ inline void wg_sums(V (&acc)[ND], int nd, Sc* sums) {
 
 // The iteration of one system by the calling workgroup (state in ss).
 template <class V, class Sc, int NB>
-__device__ void small_solve(const SmallJob<V, Sc>& J, State<Sc>& ss, Sc* sums) {
+__device__ __forceinline__ void small_solve(const SmallJob<V, Sc>& J, State<Sc>& ss, Sc* sums) {
   constexpr int NA = NB + 1;
   const int tid = threadIdx.x, N = J.N, n = J.n;
   const long long ldq = J.ldq;
@@ -224,21 +227,32 @@ __device__ void small_solve(const SmallJob<V, Sc>& J, State<Sc>& ss, Sc* sums) {
     __syncthreads();
     return nf > 0 ? program(nf, PH_COMBINE, i, j) : false;
   };
-  // G_i = gt + sum_{s<i} beta_s G_s
-  auto gcomb = [&](int i) {
+  // G_i = g0 + sum_{s<i} beta_s G_s.  Transpose-free (wi): v = A g was stored in W_i, and
+  // also W_i = v + sum_{s<i} beta_s W_s with its S column, c_i and alpha (returns true
+  // once the solve has ended); otherwise returns false.
+  auto gcomb = [&](const V* g0, int i, bool wi) {
+    clear();
     for (int r0 = tid; r0 < N; r0 += SB * UR) {
-      V v[UR];
+      V v[UR], wv[UR];
       int rows[UR];
 #pragma unroll
       for (int u = 0; u < UR; ++u) {
-        rows[u] = min(r0 + u * SB, N - 1);
-        v[u] = J.gt[rows[u]];
+        rows[u] = min(r0 + u * SB, N - 1);   // rows past N re-read row N - 1, unused
+        v[u] = g0[rows[u]];
+        wv[u] = wi ? J.W[rows[u] + (size_t)i * N] : zero<V>();
       }
       for (int s = 0; s < i; ++s) {
         const V bs = convert<V>(ss.beta[s]);
         V gv[UR];
 #pragma unroll
         for (int u = 0; u < UR; ++u) gv[u] = J.G[rows[u] + (size_t)s * N];
+        if (wi) {
+          V wa[UR];
+#pragma unroll
+          for (int u = 0; u < UR; ++u) wa[u] = J.W[rows[u] + (size_t)s * N];
+#pragma unroll
+          for (int u = 0; u < UR; ++u) wv[u] = axpy(wv[u], bs, wa[u]);
+        }
 #pragma unroll
         for (int u = 0; u < UR; ++u) v[u] = axpy(v[u], bs, gv[u]);
       }
@@ -247,9 +261,16 @@ __device__ void small_solve(const SmallJob<V, Sc>& J, State<Sc>& ss, Sc* sums) {
         const int row = r0 + u * SB;
         if (row >= N) break;
         J.G[row + (size_t)i * N] = v[u];
+        if (wi) {
+          J.W[row + (size_t)i * N] = wv[u];
+#pragma unroll
+          for (int d = 0; d < NB; ++d)
+            if (d < n - i) cdot_acc(acc[d], J.Q[row + (long long)(i + d) * ldq], wv[u]);
+        }
       }
     }
     __syncthreads();
+    return wi ? program(n - i, PH_SPMV_STEP, i, 0) : false;
   };
   // W_i = A gin (G_i = gin when gin is another vector) ; S column i, c_i, alpha
   auto step = [&](const V* gin, int i) {
@@ -261,16 +282,30 @@ __device__ void small_solve(const SmallJob<V, Sc>& J, State<Sc>& ss, Sc* sums) {
   // set-up: r_0 = b - A x_0, ||b||, e_0 ; F = A^H Q(:, 0:n-1) ; w_0 = A r_0
   spmv(J.rp, J.ci, J.val, J.x, J.r, nullptr, SM_RESID, 0, 0);
   if (program(3, PH_SETUP, 0, 0)) return;
-  for (int c = 0; c + 1 < n; ++c)
-    spmv(J.rpT, J.ciT, J.valT, J.Q + (size_t)c * ldq, J.F + (size_t)c * N, nullptr, SM_PLAIN, 0, 0);
+  if (!J.tf)
+    for (int c = 0; c + 1 < n; ++c)
+      spmv(J.rpT, J.ciT, J.valT, J.Q + (size_t)c * ldq, J.F + (size_t)c * N, nullptr, SM_PLAIN, 0, 0);
   if (step(J.r, 0)) return;
   const long long max_cycles = J.maxit / n + 2;
   for (long long jj = 0; jj <= max_cycles; ++jj) {
     const int j = jj >= 1 ? 1 : 0;
     for (int i = 1; i < n; ++i) {
       if (alpha(i - 1, i, j >= 1 ? n - i : 1, PH_INNER, i, j)) return;
+      if (J.tf) {
+        // g = z_w - g/omega (j >= 1) or r (j = 0); v = A g -> W_i with q_s^H v (s < i), beta;
+        // then g_{jn+i}, w_{jn+i} recombined with the S column
+        const V* g0 = J.r;
+        if (j >= 1) {
+          combine(i, n, 0, i, j);
+          g0 = J.gt;
+        }
+        spmv(J.rp, J.ci, J.val, g0, J.W + (size_t)i * N, nullptr, SM_STEP, 0, i);
+        if (program(i, PH_COMBINE, i, j)) return;
+        if (gcomb(g0, i, true)) return;
+        continue;
+      }
       if (combine(i, j >= 1 ? n : i, i, i, j)) return;
-      gcomb(i);
+      gcomb(J.gt, i, false);
       if (step(J.G + (size_t)i * N, i)) return;
     }
     // k = jn + n: half step, minimisation step, cycle close

@@ -3,7 +3,9 @@
 Same bars as the multi-launch parity tests (same flag, iteration counts within
 5%, x_1..x_20 within 1e-8 relative, true residual below tol, x within 1e-6 of
 the oracle's x), plus: every system of a mixed batch gives bitwise the result
-it gives in a batch of its own, and ineligible handles are refused.
+it gives in a batch of its own, and ineligible handles are refused.  Systems
+created with transpose_free run the transpose-free steps and are checked
+against the oracle's transpose-free variant.
 """
 import numpy as np
 import pytest
@@ -22,7 +24,7 @@ import torch  # noqa: E402
 from paper_1106_3678_amd import binding  # noqa: E402
 
 
-def prepare(p, record=0, maxit=None):
+def prepare(p, record=0, maxit=None, transpose_free=False):
     cplx = np.iscomplexobj(p.A.data) or np.iscomplexobj(p.b)
     dt, nt = (torch.complex128, np.complex128) if cplx else (torch.float64, np.float64)
     dA = binding.to_device(p.A)
@@ -32,7 +34,8 @@ def prepare(p, record=0, maxit=None):
     mi = p.maxit if maxit is None else maxit
     K = min(record, mi)
     it = torch.zeros((K, p.N), dtype=dt, device="cuda") if K else None
-    s = binding.Solver(dA, p.n, tol=p.tol, maxit=mi, kappa=p.kappa, record_iterates=K, iterates=it)
+    s = binding.Solver(dA, p.n, tol=p.tol, maxit=mi, kappa=p.kappa, record_iterates=K, iterates=it,
+                       transpose_free=transpose_free)
     return dict(p=p, s=s, b=b, x=x, Q=Q, it=it, dA=dA)
 
 
@@ -47,8 +50,8 @@ def run_batch(items):
     return out
 
 
-def check(p, r, x, its, K=20, x_tol=1e-6):
-    o = run_oracle(p, record=K)
+def check(p, r, x, its, K=20, x_tol=1e-6, transpose_free=False):
+    o = run_oracle(p, record=K, transpose_free=transpose_free)
     print(f"{p.name}: N={p.N} n={p.n} batch flag={r.flag} iter={r.iter} true={r.err_true:.3e} | "
           f"oracle flag={o.flag} iter={o.iter}", flush=True)
     assert r.flag == o.flag
@@ -164,3 +167,31 @@ def test_batch_refuses_ineligible():
         assert e.value.code == binding.MLB_EUNSUPPORTED
         s.close()
     d["s"].close()
+
+
+@pytest.mark.parametrize("case", ["2d_n4", "3d_n16", "complex_n8", "dense7"])
+def test_batch_transpose_free(case):
+    if case == "dense7":
+        g = np.random.default_rng(7)
+        A = sp.csr_matrix(g.standard_normal((7, 7)) / np.sqrt(7) + 2 * np.eye(7))
+        p = workloads.Problem("dense7", A, g.standard_normal(7), np.asfortranarray(g.standard_normal((7, 8))),
+                              np.zeros(7), 8, 1e-10, 100)
+    else:
+        p = {"2d_n4": lambda: workloads.config1(n=4), "3d_n16": lambda: workloads.config2(n=16, m=12, maxit=4000),
+             "complex_n8": lambda: workloads.config5(n=8, m=10, maxit=4000)}[case]()
+    (r, x, its), = run_batch([prepare(p, record=20, transpose_free=True)])
+    check(p, r, x, its, transpose_free=True)
+    if case == "dense7":
+        assert r.iter == 7
+
+
+def test_mixed_transpose_free_batch_equals_batches_of_one():
+    """Systems with and without A^H in one launch: each bitwise its batch-of-one result."""
+    probs = mixed_problems()[:6]
+    flags = [k % 2 == 1 for k in range(len(probs))]
+    alone = [run_batch([prepare(p, transpose_free=tf)])[0] for p, tf in zip(probs, flags)]
+    mixed = run_batch([prepare(p, transpose_free=tf) for p, tf in zip(probs, flags)])
+    for p, (ra, xa, _), (rm, xm, _) in zip(probs, alone, mixed):
+        assert rm.flag == ra.flag == 0, p.name
+        assert rm.iter == ra.iter, p.name
+        assert np.array_equal(xm, xa), p.name

@@ -10,8 +10,8 @@ is sampled over 24 perturbed runs: the drifted final true residual is chaotic un
 rounding (2e-11 to 4.3e-9 across 24 oracle runs of the 8x10x6 block-Jacobi case),
 so a sample of three understates it.
 Also: bitwise reruns, finite termination, the fp32 refinement and preconditioned
-modes, sequences and serving, the kernel timer, refusal by the batch kernel, and
-the 128^3 workload's first iterates in the benchmark's launch configuration.
+modes, sequences and serving (worker and batch paths), the kernel timer, and the
+128^3 workload's first iterates in the benchmark's launch configuration.
 """
 import numpy as np
 import pytest
@@ -129,7 +129,7 @@ def test_sequence_and_server_match_plain_solves():
     r1, n = seq.solve(b, x1, Q)
     seq.close()
     torch.cuda.synchronize()
-    server = binding.Server(budget_bytes=1 << 30, max_inflight=2)
+    server = binding.Server(budget_bytes=1 << 30, max_inflight=2, small_n_max=-1)   # workers only
     x2 = torch.zeros_like(x0)
     t = server.submit(dA, b, x2, Q, 4, tol=p.tol, maxit=p.maxit, transpose_free=True)
     r2, _ = server.wait(t)
@@ -137,6 +137,18 @@ def test_sequence_and_server_match_plain_solves():
     assert n == 4 and r0.flag == r1.flag == r2.flag == 0
     assert r0.iter == r1.iter == r2.iter
     assert torch.equal(x0, x1) and torch.equal(x0, x2)
+    # with the batchers on, the same small request runs in the batch kernel: bitwise a direct batch solve
+    s = binding.Solver(dA, 4, tol=p.tol, maxit=p.maxit, transpose_free=True)
+    x3 = torch.zeros_like(x0)
+    (r3,) = binding.solve_batch([s], [b], [x3], [Q])
+    s.close()
+    server = binding.Server(budget_bytes=1 << 30, max_inflight=2)
+    x4 = torch.zeros_like(x0)
+    t = server.submit(dA, b, x4, Q, 4, tol=p.tol, maxit=p.maxit, transpose_free=True)
+    r4, _ = server.wait(t)
+    server.close()
+    assert r3.flag == r4.flag == 0 and r3.iter == r4.iter
+    assert torch.equal(x3, x4)
 
 
 def test_kernel_timer_and_footprint():
@@ -155,19 +167,6 @@ def test_kernel_timer_and_footprint():
             print(f"transpose_free={tf} kernel {k}: {1e3 * ms:.1f} us")
             assert 0 < ms < 10
         s.close()
-
-
-def test_batch_refuses_transpose_free():
-    p = workloads.config1(n=4)
-    dA = binding.to_device(p.A)
-    b = torch.from_numpy(p.b).cuda()
-    x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
-    Q = binding.column_major(p.Q)
-    s = binding.Solver(dA, 4, tol=p.tol, maxit=p.maxit, transpose_free=True)
-    with pytest.raises(binding.MlbError) as e:
-        binding.solve_batch([s], [b], [x], [Q])
-    assert e.value.code == binding.MLB_EUNSUPPORTED
-    s.close()
 
 
 def test_full_size_convdiff3d_first_iterates():
