@@ -62,20 +62,32 @@ def measured_traffic(workload, root=ROOT):
     return int(m_t.group(1))
 
 
-def cpu_baseline(p, iters_gpu, sample_iters):
-    """The oracle on this host: time a bounded sample of the same solve, scale to the full iteration count."""
+def cpu_baseline(p, iters_gpu, sample_iters, target_s=15.0):
+    """The oracle on this host, on one core: a bounded sample of the same solve, scaled to the
+    GPU's iteration count.  A 5-iteration probe sets the sample length to about target_s of CPU
+    time (at most the GPU's iteration count, and at most sample_iters when that is > 0)."""
     from threadpoolctl import threadpool_limits
 
     import oracle
 
-    with threadpool_limits(limits=1):
+    def run(maxit):
         t0 = time.perf_counter()
-        o = oracle.mlbicgstabt(p.A, p.b, p.Q, x0=p.x0, tol=p.tol, maxit=sample_iters, kappa=p.kappa)
-        dt = time.perf_counter() - t0
+        o = oracle.mlbicgstabt(p.A, p.b, p.Q, x0=p.x0, tol=p.tol, maxit=maxit, kappa=p.kappa)
+        return o, time.perf_counter() - t0
+
+    with threadpool_limits(limits=1):
+        o, dt = run(5)
+        n_it = max(5, min(iters_gpu, int(target_s * o.iter / max(dt, 1e-9))))
+        if sample_iters > 0:
+            n_it = min(n_it, sample_iters)
+        if n_it > o.iter and o.flag == 1:
+            o, dt = run(n_it)
     per_it = dt / max(o.iter, 1)
-    return {"value": per_it * iters_gpu, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"first {o.iter} iterations of the same solve (setup included) took {dt:.2f} s on 1 core; "
-                      f"scaled to the GPU's {iters_gpu} iterations"}
+    whole = o.iter >= iters_gpu
+    return {"value": dt if whole else per_it * iters_gpu, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"the whole solve ({o.iter} iterations, setup included) on 1 core" if whole else
+                       f"first {o.iter} iterations of the same solve (setup included) took {dt:.2f} s on 1 core; "
+                       f"scaled to the GPU's {iters_gpu} iterations")}
 
 
 def bench_serving(args, torch, workloads, binding):
@@ -256,7 +268,8 @@ def main():
                     help="iterate without A^H (beta recurrence from q_s^H A g, w recombined)")
     ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi"],
                     help="auto: block Jacobi for the reservoir workload, none otherwise")
-    ap.add_argument("--cpu-iters", type=int, default=20, help="oracle sample length (iterations)")
+    ap.add_argument("--cpu-iters", type=int, default=0,
+                    help="cap on the oracle sample (iterations); 0: about 15 s of CPU time")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--calib-copy", type=float, default=0.0,

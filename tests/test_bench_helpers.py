@@ -46,3 +46,18 @@ def test_committed_profiles_parse():
         text = open(os.path.join(prof, f)).read()
         assert "traffic_bytes_per_launch:" in text and "kernel_source_sha256:" in text
         assert "rocprofv3 --kernel-trace --stats" in text and "rocprofv3 --pmc FETCH_SIZE" in text
+
+
+def test_cpu_baseline_sample_is_bounded():
+    """The oracle baseline runs a bounded sample: the whole solve when it is short, else about
+    target_s of CPU time scaled to the GPU's iteration count, and never beyond an explicit cap."""
+    import workloads
+
+    p = workloads.config1(n=4)
+    whole = bench.cpu_baseline(p, 69, 0, target_s=30.0)
+    assert whole["cores"] == 1 and whole["kind"] == "oracle" and "whole solve" in whole["sample"]
+    capped = bench.cpu_baseline(p, 69, 10, target_s=30.0)
+    assert "first 10 iterations" in capped["sample"]
+    assert capped["value"] > 0
+    short = bench.cpu_baseline(p, 69, 0, target_s=1e-6)
+    assert "first 5 iterations" in short["sample"]
