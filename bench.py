@@ -27,7 +27,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False):
+def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False, literal=False):
     """Algorithmic bytes of one SpMV-step launch (w_i = A g_i with q_s^H w_i, s = i..n-1),
     averaged over the launches i = 0..n-1 of one cycle.
 
@@ -35,10 +35,11 @@ def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False):
     gathered input once, n - i columns of Q and the written w_i.  (The input is
     already in its column of G: the cycle close writes g into G_0 itself.)  The
     transpose-free steps read columns 0..i-1 of Q instead (v = A g with q_s^H v,
-    s < i): the same count over a cycle, so the same average.
+    s < i): the same count over a cycle, so the same average.  In the literal
+    recurrence order only c_i = q_i^H w_i is reduced: one column of Q.
     """
     mat = nnz * ((9 if bsr else 1) * sv + 4) + 4 * (nbrows + 1)
-    vec_avg = sum(1 + (n - i) + 1 for i in range(n)) / n
+    vec_avg = 3.0 if literal else sum(1 + (n - i) + 1 for i in range(n)) / n
     return mat + vec_avg * N * sv
 
 
@@ -264,6 +265,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="number of shadow vectors (0 = the workload's)")
     ap.add_argument("--m", type=int, default=0, help="grid points per dimension (0 = the workload's)")
     ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--order", default="fused", choices=["fused", "literal"],
+                    help="recurrence order: Gram-matrix form (fused) or the sequential loops (literal)")
     ap.add_argument("--transpose-free", action="store_true",
                     help="iterate without A^H (beta recurrence from q_s^H A g, w recombined)")
     ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi"],
@@ -311,6 +314,8 @@ def main():
         profile_key += "_ir"
     if args.transpose_free:
         profile_key += "_tf"
+    if args.order == "literal":
+        profile_key += "_literal"
     nbrows = len(p.A.indptr) - 1
     log(f"[bench] generated {p.name}: N={p.N} stored={nnz} in {time.perf_counter() - t:.1f} s")
     dA = binding.to_device(p.A, dev)
@@ -324,7 +329,8 @@ def main():
     t_create = time.perf_counter()
     solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=args.inner_tol,
                             precond=binding.MLB_PRECOND_JACOBI if use_jacobi else binding.MLB_PRECOND_NONE,
-                            transpose_free=args.transpose_free)
+                            transpose_free=args.transpose_free,
+                            order=binding.MLB_ORDER_LITERAL if args.order == "literal" else binding.MLB_ORDER_FUSED)
     torch.cuda.synchronize()
     create_ms = 1e3 * (time.perf_counter() - t_create)   # validation, A^H (and M^{-1} / fp32 copies)
 
@@ -353,7 +359,7 @@ def main():
     # value bytes of the iteration that the timed kernel belongs to (fp32 inner iteration for ir)
     sv = (16 if cplx else 8) if args.precision == "fp64" else (8 if cplx else 4)
     ms_spmv = solver.time_kernel(binding.MLB_KERNEL_SPMV_STEP, args.kernel_reps)
-    bytes_spmv = spmv_step_bytes(nnz, nbrows, p.N, p.n, sv, bsr=(fmt == "bsr3"))
+    bytes_spmv = spmv_step_bytes(nnz, nbrows, p.N, p.n, sv, bsr=(fmt == "bsr3"), literal=(args.order == "literal"))
     achieved = bytes_spmv / (ms_spmv * 1e-3) / 1e9
     ms_alpha = solver.time_kernel(binding.MLB_KERNEL_ALPHA_STEP, args.kernel_reps)
     ms_comb = solver.time_kernel(binding.MLB_KERNEL_COMBINE, args.kernel_reps)
@@ -397,6 +403,7 @@ def main():
             "precision": args.precision,
             "preconditioner": "block Jacobi (right)" if use_jacobi else "none",
             "variant": "transpose-free (no A^H)" if args.transpose_free else "Algorithm 7.1 (explicit A^H)",
+            "recurrence_order": args.order,
             "iterations": int(last.iter),
             "outer_iters": int(last.outer_iters),
             "fp64_iters": int(last.fp64_iters),

@@ -125,7 +125,20 @@ typedef struct {
   void* iterates;           /* device, N x record_iterates, or NULL            */
   int32_t precond;          /* MLB_PRECOND_NONE or MLB_PRECOND_JACOBI          */
   int32_t transpose_free;   /* 0: Algorithm 7.1 with A^H; 1: without A^H       */
+  int32_t order;            /* MLB_ORDER_FUSED (0) or MLB_ORDER_LITERAL (1)    */
 } mlb_options;
+
+/*
+ * Order of the beta~ and beta recurrences (Algorithm 7.1, the two loops of an
+ * inner step).  MLB_ORDER_FUSED (default) evaluates each recurrence from small
+ * Gram matrices of inner products the passes already produce: equal in exact
+ * arithmetic, three reductions per step whatever n is.  MLB_ORDER_LITERAL runs
+ * them in the algorithm's own sequential order: each coefficient from the
+ * inner product of the vector the previous coefficient updated, one reduction
+ * and one pass per coefficient (n + 2 reductions per step).  Not combined with
+ * transpose_free (MLB_EUNSUPPORTED); mlbicgstab_solve_batch refuses it.
+ */
+enum { MLB_ORDER_FUSED = 0, MLB_ORDER_LITERAL = 1 };
 
 typedef struct {
   int32_t flag;             /* same as the return code when >= -1              */
@@ -169,7 +182,7 @@ int mlbicgstab_solve(mlb_handle h, const void* b, void* x, const void* Q, int64_
  * (an addition of this library, for many small systems, whose multi-launch
  * iteration is bound by launch latency rather than bandwidth).  Every h[k]
  * must come from mlbicgstab_create with a CSR matrix of at most
- * MLB_BATCH_MAX_N rows, MLB_PREC_FP64 and MLB_PRECOND_NONE (an iterate
+ * MLB_BATCH_MAX_N rows, MLB_PREC_FP64, MLB_PRECOND_NONE and MLB_ORDER_FUSED (an iterate
  * record is kept as in a solve; transpose_free handles run the transpose-free
  * steps); all on the same stream and of the same value type (else
  * MLB_EINVAL / MLB_EUNSUPPORTED, and nothing runs).  b[k], x[k], Q[k], ldq[k]
@@ -248,7 +261,7 @@ enum {
  *
  * A server owns max_inflight workers, each with its own HIP stream, and (when
  * small_n_max >= 0) two batchers with a stream each.  Small requests (CSR,
- * fp64, no preconditioner, no iterate record, N <= small_n_max) wait for the
+ * fp64, fused order, no preconditioner, no iterate record, N <= small_n_max) wait for the
  * batchers; a free batcher takes every waiting small request that fits (at
  * most 256) and solves them in one launch of mlbicgstab_solve_batch's kernel.
  * Other requests wait for the workers, which run create, solve and destroy

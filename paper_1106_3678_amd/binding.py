@@ -19,6 +19,7 @@ MLB_R64, MLB_C128 = 0, 1
 MLB_CSR, MLB_BSR3 = 0, 1
 MLB_PREC_FP64, MLB_PREC_FP32_IR = 0, 1
 MLB_PRECOND_NONE, MLB_PRECOND_JACOBI = 0, 1
+MLB_ORDER_FUSED, MLB_ORDER_LITERAL = 0, 1
 MLB_MAX_N = 32
 MLB_KERNEL_SPMV_STEP, MLB_KERNEL_ALPHA_STEP, MLB_KERNEL_COMBINE, MLB_KERNEL_RECOMBINE = 0, 1, 2, 3
 
@@ -48,6 +49,7 @@ class mlb_options(ctypes.Structure):
         ("iterates", ctypes.c_void_p),
         ("precond", ctypes.c_int32),
         ("transpose_free", ctypes.c_int32),
+        ("order", ctypes.c_int32),
     ]
 
 
@@ -337,14 +339,15 @@ class Solver:
     def __init__(self, dmat: DeviceMatrix, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
                  precision: int = MLB_PREC_FP64, inner_tol: float = 0.0, max_outer: int = 0,
                  record_iterates: int = 0, iterates=None, stream=None, precond: int = MLB_PRECOND_NONE,
-                 transpose_free: bool = False):
+                 transpose_free: bool = False, order: int = MLB_ORDER_FUSED):
         import torch
 
         self.dmat = dmat
         self.n = n
         self.iterates = iterates
         self.opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, max_outer, record_iterates,
-                               iterates.data_ptr() if iterates is not None else None, precond, int(transpose_free))
+                               iterates.data_ptr() if iterates is not None else None, precond, int(transpose_free),
+                               order)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.h = mlbicgstab_create(dmat.descriptor(), self.opt, self.stream.cuda_stream)
 
@@ -389,12 +392,12 @@ class Sequence:
 
     def __init__(self, dmat: DeviceMatrix, n: int, n_min: int, n_max: int, step: int, tol: float = 1e-10,
                  maxit: int = 1000, kappa: float = 0.0, precision: int = MLB_PREC_FP64, stream=None,
-                 precond: int = MLB_PRECOND_NONE, transpose_free: bool = False):
+                 precond: int = MLB_PRECOND_NONE, transpose_free: bool = False, order: int = MLB_ORDER_FUSED):
         import torch
 
         self.dmat = dmat
         self.n_max = n_max
-        self.opt = mlb_options(n, tol, maxit, kappa, precision, 0.0, 0, 0, None, precond, int(transpose_free))
+        self.opt = mlb_options(n, tol, maxit, kappa, precision, 0.0, 0, 0, None, precond, int(transpose_free), order)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.h = mlb_sequence_create(dmat.descriptor(), self.opt, n_min, n_max, step, self.stream.cuda_stream)
 
@@ -427,10 +430,11 @@ class Server:
 
     def submit(self, dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
                precision: int = MLB_PREC_FP64, inner_tol: float = 0.0, precond: int = MLB_PRECOND_NONE,
-               transpose_free: bool = False) -> int:
+               transpose_free: bool = False, order: int = MLB_ORDER_FUSED) -> int:
         N = dmat.nrows
         ldq = q_layout(Q, N, n)
-        opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, 0, 0, None, precond, int(transpose_free))
+        opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, 0, 0, None, precond, int(transpose_free),
+                          order)
         t = mlb_server_submit(self.h, dmat.descriptor(), opt, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
         self._keep[t] = (dmat, b, x, Q)
         return t

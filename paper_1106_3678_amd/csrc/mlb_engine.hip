@@ -293,6 +293,7 @@ struct Engine {
 
   bool own_flag = true;
   bool tf = false;   // transpose-free inner steps: no A^H, no F (set before init)
+  bool literal = false;   // beta~ and beta recurrences in the sequential order, one reduction per coefficient
 
   // ext_flag: a pinned, host-mapped int the caller owns (serving workers reuse one
   // per worker); NULL = allocate one.
@@ -475,12 +476,13 @@ struct Engine {
   }
   // w_i = A G_i ; S[s][i] = q_s^H w_i, s = i..n-1.  With gin != G_i the input is
   // also copied to G_i (cycle close and set-up, where g_k = g).
+  // The literal order needs only c_i = q_i^H w_i (nd = 1).
   void spmv_step(const V* gin, int i, int flags = 0) {
     SpmvArgs<V> a{};
     a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
     V* Gi = G + (size_t)i * N;
     a.xin = gin; a.out1 = W + (size_t)i * N; a.out2 = gin == Gi ? nullptr : Gi;
-    a.Q = Q; a.ldq = ldq; a.d0 = i; a.nd = n - i;
+    a.Q = Q; a.ldq = ldq; a.d0 = i; a.nd = literal ? 1 : n - i;
     flags |= force_flags;
     const Timed tm = timed(MLB_KERNEL_SPMV_STEP);
     switch (nb) {
@@ -489,7 +491,7 @@ struct Engine {
       case 16: launch_spmv_nd<V, Sc, SM_STEP, 16>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
       default: launch_spmv_nd<V, Sc, SM_STEP, 32>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
     }
-    if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, std::max(nb, 3), n - i, PH_SPMV_STEP, i, 0);
+    if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, std::max(nb, 3), a.nd, PH_SPMV_STEP, i, 0);
   }
   void alpha(V* x, int i_prev, int d0, int nd, int phase, int i, int j, V* xrec, long long K, int flags = 0) {
     const V* gh = G + (size_t)i_prev * N;
@@ -508,7 +510,9 @@ struct Engine {
     if (!(flags & F_SKIP_SCALAR)) scalar(grid_vec, nb + 1, nd + 1, phase, i, j);
   }
   // out: gt (inner steps) or G_0 (cycle close)
-  void combine(int t0, int t1, int nf, int i, int j, V* out, int flags = 0) {
+  // phase / pi: the recurrence run on the f_s^H g sums (the literal order takes
+  // beta_0 from f_0^H r with PH_LIT_B)
+  void combine(int t0, int t1, int nf, int i, int j, V* out, int flags = 0, int phase = PH_COMBINE, int pi = -1) {
     flags |= force_flags;
     const Timed tm = timed(MLB_KERNEL_COMBINE);
 #define MLB_COMB(B)                                                                                            \
@@ -521,11 +525,40 @@ struct Engine {
       default: MLB_COMB(32); break;
     }
 #undef MLB_COMB
-    if (!(flags & F_SKIP_SCALAR) && nf > 0) scalar(grid_vec, nb, nf, PH_COMBINE, i, j);
+    if (!(flags & F_SKIP_SCALAR) && nf > 0) scalar(grid_vec, nb, nf, phase, pi >= 0 ? pi : i, j);
+  }
+  // Literal order: the beta~ passes of step i (coefficients i..n-1; z_w in gt,
+  // the g sum in z), the last writing g into gout with f_0^H g (i >= 1), each
+  // followed by the one-coefficient recurrence.
+  void lit_tilde(int i, V* gout) {
+    const int flags = force_flags;
+    for (int sidx = i; sidx < n; ++sidx) {
+      const int first = sidx == i, last = sidx == n - 1;
+      const V* qf = last ? (i >= 1 ? (const V*)F : nullptr) : Q + (size_t)(sidx + 1) * ldq;
+      const int nf = last ? (i >= 1 ? 1 : 0) : 1;
+      const Timed tm = timed(MLB_KERNEL_COMBINE);
+      MLB_LAUNCH((k_lit_tilde<V, Sc>), grid_vec, s, tm, st, part, N, sidx, first, last, (const V*)r,
+                 (const V*)(W + (size_t)sidx * N), (const V*)(G + (size_t)sidx * N), gt, z, gout, qf, nf, flags);
+      if (!last) scalar(grid_vec, 4, 1, PH_LIT_T, sidx + 1, 0);
+      else if (nf) scalar(grid_vec, 4, 1, PH_LIT_B, 0, 0);
+    }
+  }
+  // Literal order: the beta passes of step i (coefficients 0..i-1) on g in gt;
+  // the last writes g_{jn+i} into G_i.
+  void lit_beta(int i) {
+    const int flags = force_flags;
+    for (int sidx = 0; sidx < i; ++sidx) {
+      const int last = sidx == i - 1;
+      const Timed tm = timed(MLB_KERNEL_RECOMBINE);
+      MLB_LAUNCH((k_lit_beta<V, Sc>), grid_vec, s, tm, st, part, N, sidx, last, gt, (const V*)(G + (size_t)sidx * N),
+                 G + (size_t)i * N, last ? (const V*)nullptr : (const V*)(F + (size_t)(sidx + 1) * N), flags);
+      if (!last) scalar(grid_vec, 4, 1, PH_LIT_B, sidx + 1, 0);
+    }
   }
   void omega_update(V* x, V* xrec, long long K) {
+    const int nq = literal ? 1 : n;   // the literal order needs only e = q_1^H r here
 #define MLB_OM(B) \
-  k_omega<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, r, z, Q, ldq, n, xrec, K, PH_OMEGA_UPD, n, force_flags)
+  k_omega<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, r, z, Q, ldq, nq, xrec, K, PH_OMEGA_UPD, n, force_flags)
     switch (nb) {
       case 4: MLB_OM(4); break;
       case 8: MLB_OM(8); break;
@@ -533,13 +566,36 @@ struct Engine {
       default: MLB_OM(32); break;
     }
 #undef MLB_OM
-    scalar(grid_vec, nb + 1, n + 1, PH_OMEGA_UPD, 0, 1);
+    scalar(grid_vec, nb + 1, nq + 1, literal ? PH_OMEGA_LIT : PH_OMEGA_UPD, 0, 1);
   }
 
   // ---- the iteration ----------------------------------------------------
 
+  // Steps k = jn+1 .. jn+n of cycle j in the literal order of Algorithm 7.1: each
+  // coefficient of the beta~ and beta recurrences from its own reduction, on the
+  // vector the previous coefficient updated.
+  void cycle_literal(int j, V* x, V* xrec, long long K) {
+    for (int i = 1; i < n; ++i) {
+      // x, r update; e = q_{i+1}^H r (no beta~ list: j = 0 for the recurrence)
+      alpha(x, i - 1, i, 1, PH_INNER, i, 0, xrec, K);
+      if (j >= 1) lit_tilde(i, gt);                         // g = z_w - g/omega, f_0^H g
+      else combine(i, i, 1, i, 0, gt, 0, PH_LIT_B, 0);      // g = r, f_0^H r
+      lit_beta(i);                                          // g_{jn+i} -> G_i
+      spmv_step(G + (size_t)i * N, i);                      // w, c_i, alpha
+    }
+    alpha(x, n - 1, 0, 0, PH_HALF, n, j, xrec, K);
+    spmv_omega(r, z);
+    omega_update(x, xrec, K);
+    lit_tilde(0, G);   // g_{jn+n} straight into G_0
+    spmv_step(G, 0);
+  }
+
   // Steps k = jn+1 .. jn+n of cycle j (Algorithm 7.1, i/j form).
   void cycle(int j, V* x, V* xrec, long long K) {
+    if (literal) {
+      cycle_literal(j, x, xrec, K);
+      return;
+    }
     for (int i = 1; i < n; ++i) {
       // x_{jn+i} = x + alpha g ; r_{jn+i} = r - alpha w ; e = q_{i+1}^H r (and q_s^H r, s > i, when j >= 1)
       alpha(x, i - 1, i, j >= 1 ? n - i : 1, PH_INNER, i, j, xrec, K);
@@ -692,6 +748,10 @@ static void check_options(const mlb_options* opt) {
   if (opt->precond != MLB_PRECOND_NONE && opt->precond != MLB_PRECOND_JACOBI)
     throw Error{MLB_EINVAL, "precond must be MLB_PRECOND_NONE or MLB_PRECOND_JACOBI"};
   if (opt->transpose_free != 0 && opt->transpose_free != 1) throw Error{MLB_EINVAL, "transpose_free must be 0 or 1"};
+  if (opt->order != MLB_ORDER_FUSED && opt->order != MLB_ORDER_LITERAL)
+    throw Error{MLB_EINVAL, "order must be MLB_ORDER_FUSED or MLB_ORDER_LITERAL"};
+  if (opt->order == MLB_ORDER_LITERAL && opt->transpose_free)
+    throw Error{MLB_EUNSUPPORTED, "the literal order is not combined with transpose_free"};
   if (opt->record_iterates < 0) throw Error{MLB_EINVAL, "record_iterates must be >= 0"};
   if (opt->record_iterates > 0) {
     if (!opt->iterates) throw Error{MLB_EINVAL, "record_iterates > 0 needs an iterates buffer"};
@@ -769,6 +829,7 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
   const bool tf = h->opt.transpose_free != 0;
   const Mat<V64> AH = tf ? Mat<V64>{} : build_transpose(A, h->al, h->s);
   im.e64.tf = tf;
+  im.e64.literal = h->opt.order == MLB_ORDER_LITERAL;
   im.e64.init(A, AH, h->opt.n, h->s, h->al, h->ext_flags);
   im.r64 = h->al.get<V64>(h->N);
   if (h->opt.precision == MLB_PREC_FP32_IR) {
@@ -794,6 +855,7 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
     A32.lpr = A.lpr;
     AH32.lpr = AH.lpr;
     im.e32.tf = tf;
+    im.e32.literal = h->opt.order == MLB_ORDER_LITERAL;
     im.e32.init(A32, AH32, h->opt.n, h->s, h->al, h->ext_flags ? h->ext_flags + 1 : nullptr);
     im.has32 = true;
     im.b32 = h->al.get<V32>(h->N);
@@ -1075,6 +1137,7 @@ static void check_batchable(const mlb_solver* h) {
   if (h->format != MLB_CSR) throw Error{MLB_EUNSUPPORTED, "batched solves take CSR matrices"};
   if (h->opt.precision != MLB_PREC_FP64) throw Error{MLB_EUNSUPPORTED, "batched solves run in fp64"};
   if (h->opt.precond != MLB_PRECOND_NONE) throw Error{MLB_EUNSUPPORTED, "batched solves take no preconditioner"};
+  if (h->opt.order != MLB_ORDER_FUSED) throw Error{MLB_EUNSUPPORTED, "batched solves run the fused order"};
   if (h->N > MLB_BATCH_MAX_N) throw Error{MLB_EUNSUPPORTED, "batched solves take at most MLB_BATCH_MAX_N rows"};
 }
 
@@ -1640,7 +1703,7 @@ int mlb_server_submit(mlb_server_handle S, const mlb_matrix* A, const mlb_option
       r->t_submit = now_s();
       S->table[r->ticket] = r;
       r->small = A->format == MLB_CSR && opt->precision == MLB_PREC_FP64 && opt->precond == MLB_PRECOND_NONE &&
-                 opt->record_iterates == 0 && A->nrows <= S->small_n_max;
+                 opt->record_iterates == 0 && opt->order == MLB_ORDER_FUSED && A->nrows <= S->small_n_max;
       (r->small ? S->small_queue : S->queue).push_back(r);
       *ticket = r->ticket;
     }

@@ -67,7 +67,11 @@ enum Phase : int {
   PH_COMBINE = 4,     // after g = r + sum t w - sum t/omega g: beta coefficients
   PH_SPMV_STEP = 5,   // after w = A g + ...: S column, c, next alpha
   PH_SPMV_OMEGA = 6,  // after z = A u: omega (eq. (5.1))
-  PH_OMEGA_UPD = 7    // after x += omega u, r = u - omega z: err, e, beta~ of the cycle close
+  PH_OMEGA_UPD = 7,   // after x += omega u, r = u - omega z: err, e, beta~ of the cycle close
+  // the sequential (literal) order of the recurrences: one coefficient per reduction
+  PH_LIT_T = 8,       // after a beta~ pass: t_i = -(q_i^H z_w) / c_i (i = the coefficient's index)
+  PH_LIT_B = 9,       // after a beta pass: beta_i = -(f_i^H g) / c_i
+  PH_OMEGA_LIT = 10   // as PH_OMEGA_UPD, without the beta~ list (computed pass by pass)
 };
 
 // Everything the recurrences need, resident in device memory.  Written only
@@ -307,6 +311,13 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (w0) st->omega = om;
       break;
     }
+    case PH_LIT_T:
+      if (w0) st->t[i] = zero<Sc>() - sums[0] * st->cinv[i];
+      break;
+    case PH_LIT_B:
+      if (w0) st->beta[i] = zero<Sc>() - sums[0] * st->cinv[i];
+      break;
+    case PH_OMEGA_LIT:
     case PH_OMEGA_UPD: {
       const long long k = st->iter + 1;
       double err = sqrt(re(sums[0])) / st->bnrm2;
@@ -319,7 +330,7 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (k >= st->maxit) { finish(st, 1); break; }
       if (stagnated(st, err, k)) { finish(st, 2); break; }
       if (w0) st->e = sums[1];               // e = q_1^H r
-      beta_tilde(st, sums + 1, 0, n);
+      if (phase == PH_OMEGA_UPD) beta_tilde(st, sums + 1, 0, n);
       break;
     }
   }
@@ -600,6 +611,66 @@ __global__ __launch_bounds__(BLOCK) void k_gwcomb(State<Sc>* st, Sc* partial, in
   }
   if (flags & F_SKIP_SCALAR) return;
   block_partials<ND>(acc, nd, partial);
+}
+
+// Literal order, one pass of the beta~ recurrence (coefficient s, paired with
+// q_s, w_s, g_s, c_s): z_w += t_s W_s and gs += t_s G_s, where the first pass
+// starts from z_w = r, gs = 0 with t_s = -e / c_s.  The sum is the next
+// coefficient's q_{s+1}^H z_w; the last pass instead forms g = z_w - gs / omega
+// into gout, with f_0^H g when nf = 1 (inner steps).  z_w and gs live in zw and
+// gsum; gout may be zw (each row read before the same thread writes it) or a G
+// column read by the pass (n = 1 at the cycle close).
+template <class V, class Sc>
+__global__ __launch_bounds__(BLOCK) void k_lit_tilde(State<Sc>* st, Sc* partial, int N, int s, int first, int last,
+                                                     const V* __restrict__ r, const V* __restrict__ Ws, const V* Gs,
+                                                     V* zw, V* __restrict__ gsum, V* gout, const V* __restrict__ qf,
+                                                     int nf, int flags) {
+  const int done = st->done;
+  const Sc t = first ? zero<Sc>() - st->e * st->cinv[s] : st->t[s];
+  const Sc mw = zero<Sc>() - sc_div(from_real<Sc>(1.0), st->omega);
+  if (!(flags & F_IGNORE_DONE) && done) return;
+  const V tv = convert<V>(t), mwv = convert<V>(mw);
+  V acc[4] = {zero<V>(), zero<V>(), zero<V>(), zero<V>()};
+  for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
+    const V z = axpy(first ? r[row] : zw[row], tv, Ws[row]);
+    const V g = axpy(first ? zero<V>() : gsum[row], tv, Gs[row]);
+    if (last) {
+      const V gv = axpy(z, mwv, g);
+      gout[row] = gv;
+      if (nf) cdot_acc(acc[0], qf[row], gv);
+    } else {
+      zw[row] = z;
+      gsum[row] = g;
+      cdot_acc(acc[0], qf[row], z);
+    }
+  }
+  if ((flags & F_SKIP_SCALAR) || (last && !nf)) return;
+  block_partials<4>(acc, 1, partial);
+}
+
+// Literal order, one pass of the beta recurrence (coefficient s, paired with
+// f_s, g_s, c_s): g += beta_s G_s in place; the sum is the next coefficient's
+// f_{s+1}^H g.  The last pass writes g_k into gout (its G column) instead.
+template <class V, class Sc>
+__global__ __launch_bounds__(BLOCK) void k_lit_beta(State<Sc>* st, Sc* partial, int N, int s, int last, V* g,
+                                                    const V* __restrict__ Gs, V* __restrict__ gout,
+                                                    const V* __restrict__ fnext, int flags) {
+  const int done = st->done;
+  const Sc b = st->beta[s];
+  if (!(flags & F_IGNORE_DONE) && done) return;
+  const V bv = convert<V>(b);
+  V acc[4] = {zero<V>(), zero<V>(), zero<V>(), zero<V>()};
+  for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
+    const V v = axpy(g[row], bv, Gs[row]);
+    if (last) {
+      gout[row] = v;
+    } else {
+      g[row] = v;
+      cdot_acc(acc[0], fnext[row], v);
+    }
+  }
+  if ((flags & F_SKIP_SCALAR) || last) return;
+  block_partials<4>(acc, 1, partial);
 }
 
 // x += omega u ; r = u - omega z (u held in r) ; sums: ||r||^2, q_s^H r, s < nd.

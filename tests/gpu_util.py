@@ -31,7 +31,8 @@ def block_jacobi(A):
     return (lambda v: v / d, lambda v: v / np.conj(d))
 
 
-def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None, precond=0, transpose_free=False):
+def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None, precond=0, transpose_free=False,
+            order=0):
     """Solve problem p on the GPU; returns (result, x, iterates or None)."""
     from paper_1106_3678_amd import binding
 
@@ -46,7 +47,7 @@ def run_gpu(p, precision=0, record=0, inner_tol=0.0, maxit=None, kappa=None, pre
     it = torch.zeros((K, p.N), dtype=dt, device="cuda") if K else None
     s = binding.Solver(dA, p.n, tol=p.tol, maxit=mi, kappa=p.kappa if kappa is None else kappa,
                        precision=precision, inner_tol=inner_tol, record_iterates=K, iterates=it, precond=precond,
-                       transpose_free=transpose_free)
+                       transpose_free=transpose_free, order=order)
     try:
         res = s.solve(b, x, Q)
         torch.cuda.synchronize()

@@ -61,3 +61,11 @@ def test_cpu_baseline_sample_is_bounded():
     assert capped["value"] > 0
     short = bench.cpu_baseline(p, 69, 0, target_s=1e-6)
     assert "first 5 iterations" in short["sample"]
+
+
+def test_spmv_step_bytes_literal_order():
+    """The literal order reduces one column of Q per SpMV step: input, one column, output."""
+    nnz, N, n, sv = 7000, 1000, 8, 8
+    mat = nnz * (sv + 4) + 4 * (N + 1)
+    assert bench.spmv_step_bytes(nnz, N, N, n, sv, literal=True) == mat + 3 * N * sv
+    assert bench.spmv_step_bytes(nnz, N, N, n, sv) > bench.spmv_step_bytes(nnz, N, N, n, sv, literal=True)
