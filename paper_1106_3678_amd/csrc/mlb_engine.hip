@@ -222,8 +222,8 @@ static int launch_spmv_nd(const Mat<V>& A, int grid, hipStream_t s, State<Sc>* s
     if (!grid) return occupancy_of(k_spmv_csrw<V, Sc, ND, L, MODE>);                                        \
     MLB_LAUNCH((k_spmv_csrw<V, Sc, ND, L, MODE>), grid, s, tm, st, part, a, flags);                         \
   } else {                                                                                                   \
-    if (!grid) return occupancy_of(k_spmv<V, Sc, ND, L, 1, MODE>);                                          \
-    MLB_LAUNCH((k_spmv<V, Sc, ND, L, 1, MODE>), grid, s, tm, st, part, a, phase, i, j, n, flags);            \
+    if (!grid) return occupancy_of(k_spmv_bsrw<V, Sc, ND, L, MODE>);                                        \
+    MLB_LAUNCH((k_spmv_bsrw<V, Sc, ND, L, MODE>), grid, s, tm, st, part, a, flags);                         \
   }
   switch (A.lpr) {
     case 4: MLB_SPMV_WCASE(4) break;
@@ -343,13 +343,13 @@ struct Engine {
     }
     grid_vec = grid_for(N, std::min(MAX_GRID, 8 * cus));
     grid_spmv = grid_for(A.nbrows, std::min(MAX_GRID, occ * cus));
-    // The LDS-tile SpMV (BSR3, long CSR rows) takes 256-row tiles in rounds of
-    // the grid: the smallest grid with the same number of rounds gives every
-    // workgroup the same number of tiles, instead of a last round that is only
-    // partly filled while the rest waits (BSR3 step 186 -> 181 us at 60x220x85).
-    // The wave-local CSR kernel and the vector passes keep the full grid: for
-    // them the lower occupancy costs more than the imbalance.
-    if (!(A.format == MLB_CSR && A.lpr <= 8)) {
+    // The LDS-tile SpMV (rows of more than 8 entries or blocks) takes 256-row
+    // tiles in rounds of the grid: the smallest grid with the same number of
+    // rounds gives every workgroup the same number of tiles, instead of a last
+    // round that is only partly filled while the rest waits.  The wave-local
+    // kernels and the vector passes keep the full grid: for them the lower
+    // occupancy costs more than the imbalance.
+    if (A.lpr > 8) {
       const long long tiles = (A.nbrows + BLOCK - 1) / BLOCK;
       const long long rounds = (tiles + grid_spmv - 1) / grid_spmv;
       grid_spmv = (int)std::max(1LL, (tiles + rounds - 1) / rounds);

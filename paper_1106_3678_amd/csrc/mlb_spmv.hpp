@@ -235,6 +235,110 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(State<Sc>* st, Sc* partial, Spmv
   block_partials<NA>(acc, nsum, partial);
 }
 
+// BSR3 SpMV with LPR <= 8 lanes per block row, wave-local: each wave computes
+// 64 consecutive block rows (LPR passes of 64/LPR block rows; lane `sub` of a
+// row's group takes blocks sub, sub + LPR, ...), reduces each block row's three
+// sums within its lane group, puts them in the wave's LDS slice in row order
+// and runs the epilogue on the tile's 192 scalar rows, three rounds of one row
+// per lane (coalesced).  The block-row bounds come from one row-pointer load
+// per lane and lane shuffles, the next tile's pointers loaded while the current
+// tile is processed.  No workgroup barrier, so waves stream independently.
+template <class V, class Sc, int ND, int LPR, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_spmv_bsrw(State<Sc>* st, Sc* partial, SpmvArgs<V> a, int flags) {
+  const int done = st->done;   // tested once the first row pointers are in flight
+  constexpr int NA = ND > 3 ? ND : 3;
+  constexpr int RPP = WAVE / LPR;
+  V acc[NA];
+#pragma unroll
+  for (int d = 0; d < NA; ++d) acc[d] = zero<V>();
+  const int lane = threadIdx.x % WAVE;
+  const int sub = lane % LPR, grp = lane / LPR;
+  const int nwt = (a.nbrows + WAVE - 1) / WAVE;                 // wave tiles of 64 block rows
+  __shared__ V tr[3 * BLOCK];                                   // 192 scalar row sums per wave
+  const int wslot = (threadIdx.x / WAVE) * (3 * WAVE);
+  const int wglobal = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
+  const int wstride = gridDim.x * (BLOCK / WAVE);
+  auto rp_at = [&](int t, int off) { return a.rp[min((long long)t * WAVE + off, (long long)a.nbrows)]; };
+  int rpl = 0, rpn = 0;
+  if (wglobal < nwt) {
+    rpl = rp_at(wglobal, lane);
+    rpn = rp_at(wglobal, WAVE);
+  }
+  if (!(flags & F_IGNORE_DONE) && done) return;
+  for (int wt = wglobal; wt < nwt; wt += wstride) {
+    const int brow0 = wt * WAVE;
+    int beg[LPR], end[LPR];
+#pragma unroll
+    for (int p = 0; p < LPR; ++p) {
+      const int idx = p * RPP + grp;   // block row - brow0
+      beg[p] = __shfl(rpl, idx, WAVE);
+      const int e = __shfl(rpl, (idx + 1) & (WAVE - 1), WAVE);
+      end[p] = idx == WAVE - 1 ? rpn : e;
+    }
+    if (wt + wstride < nwt) {
+      rpl = rp_at(wt + wstride, lane);
+      rpn = rp_at(wt + wstride, WAVE);
+    }
+#pragma unroll 2
+    for (int p = 0; p < LPR; ++p) {
+      V a0 = zero<V>(), a1 = zero<V>(), a2 = zero<V>();
+      for (int q = beg[p] + sub; q < end[p]; q += LPR) {
+        const V* blk = a.val + (size_t)9 * q;
+        const int c3 = 3 * a.ci[q];
+        const V x0 = a.xin[c3], x1 = a.xin[c3 + 1], x2 = a.xin[c3 + 2];
+        a0 = axpy(axpy(axpy(a0, blk[0], x0), blk[1], x1), blk[2], x2);
+        a1 = axpy(axpy(axpy(a1, blk[3], x0), blk[4], x1), blk[5], x2);
+        a2 = axpy(axpy(axpy(a2, blk[6], x0), blk[7], x1), blk[8], x2);
+      }
+      a0 = group_sum<LPR>(a0);
+      a1 = group_sum<LPR>(a1);
+      a2 = group_sum<LPR>(a2);
+      if (sub == 0) {
+        const int lb = p * RPP + grp;
+        tr[wslot + 3 * lb] = a0;
+        tr[wslot + 3 * lb + 1] = a1;
+        tr[wslot + 3 * lb + 2] = a2;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    V ys[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ys[c] = tr[wslot + c * WAVE + lane];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int row = 3 * brow0 + c * WAVE + lane;
+      if (row >= a.nrows) break;
+      const V y = ys[c];
+      if constexpr (MODE == SM_PLAIN) {
+        a.out1[row] = y;
+      } else if constexpr (MODE == SM_RESID) {
+        V bv = a.b[row];
+        V rv = bv - y;
+        a.out1[row] = rv;
+        cdot_acc(acc[0], rv, rv);
+        cdot_acc(acc[1], bv, bv);
+        if (a.nd > 0) cdot_acc(acc[2], a.Q[row], rv);
+      } else if constexpr (MODE == SM_STEP) {
+        a.out1[row] = y;
+        if (a.out2) a.out2[row] = a.xin[row];
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+          if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
+      } else {  // SM_OMEGA
+        a.out1[row] = y;
+        cdot_acc(acc[0], y, y);
+        cdot_acc(acc[1], y, a.xin[row]);
+      }
+    }
+  }
+  if (MODE == SM_PLAIN || (flags & F_SKIP_SCALAR)) return;
+  const int nsum = MODE == SM_RESID ? 3 : (MODE == SM_OMEGA ? 2 : a.nd);
+  block_partials<NA>(acc, nsum, partial);
+}
+
 // CSR SpMV with LPR <= 8 lanes per row, wave-local: each wave computes 64
 // consecutive rows (LPR passes of 64/LPR rows, all loads of a stage issued
 // together), moves each row sum to lane "row - first row" with shuffles and

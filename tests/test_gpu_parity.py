@@ -17,7 +17,7 @@ if not gpu_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 
-def check_parity(p, K=20, x_tol=1e-6, sensitive=False, precond=0):
+def check_parity(p, K=20, x_tol=1e-6, sensitive=False, precond=0, n_perturb=1):
     """Strict bars; with sensitive=True each bar is widened to what the oracle's own
     rounding-level spread (tests.gpu_util.oracle_spread) allows.  precond=1 compares
     Algorithm 7.1 with M = the block diagonal of A on both sides."""
@@ -25,7 +25,7 @@ def check_parity(p, K=20, x_tol=1e-6, sensitive=False, precond=0):
     o = run_oracle(p, record=K, precond=precond)
     it_tol, n_tol, res_tol = 1e-8, max(1, int(0.05 * o.iter)), p.tol + 1e-12
     if sensitive:
-        s_it, s_n, s_true, s_x = oracle_spread(p, o, K, precond=precond)
+        s_it, s_n, s_true, s_x = oracle_spread(p, o, K, precond=precond, n_perturb=n_perturb)
         it_tol = max(it_tol, 10 * s_it)
         n_tol = max(n_tol, 2 * s_n)
         res_tol = max(res_tol, 3 * s_true)
@@ -69,16 +69,20 @@ def test_convdiff3d_48():
 
 @pytest.mark.parametrize("grid,n", [((8, 10, 6), 4), ((12, 16, 6), 8), ((9, 14, 7), 4)])
 def test_bsr3_small(grid, n):
-    """Reservoir-shaped 3x3-block systems (cond ~ 1e6).  Summing the oracle's own inner products
-    in another order moves its iteration count by up to ~10% and, on the 9x14x7 grid, its x_20 by
-    ~1e-6, so these cases use bars derived from the oracle's rounding-order spread."""
-    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), sensitive=True)
+    """Reservoir-shaped 3x3-block systems (cond ~ 1e6), no preconditioner.  Rounding alone moves
+    the oracle's own iteration count widely here: over 24 perturbed runs, 1472-1659 (8x10x6),
+    2854-4058 (12x16x6, n = 8) and 2638-3453 (9x14x7) against 1482, 3116 and 2786, and its x_20 by
+    ~1e-6 on the 9x14x7 grid.  So these cases use bars derived from the oracle's spread over 24
+    perturbed runs (three understate it)."""
+    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), sensitive=True, n_perturb=24)
 
 
 @pytest.mark.parametrize("grid,n", [((8, 10, 6), 4), ((12, 16, 6), 8), ((9, 14, 7), 4)])
 def test_bsr3_block_jacobi(grid, n):
-    """Algorithm 7.1 with M = 3x3 block diagonal of A (right preconditioning) on the reservoir systems."""
-    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), precond=1, sensitive=True)
+    """Algorithm 7.1 with M = 3x3 block diagonal of A (right preconditioning) on the reservoir systems.
+    The iteration count still moves with rounding (over 24 perturbed oracle runs: 139-158 on 8x10x6,
+    153-173 on 9x14x7, always 165 on 12x16x6), so the bars use the spread of 24 runs."""
+    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), precond=1, sensitive=True, n_perturb=24)
 
 
 @pytest.mark.parametrize("n", [1, 4])
