@@ -1,6 +1,9 @@
 // Host side of the ML(n)BiCGStab library: the C ABI of include/mlbicgstab.h,
-// the per-cycle launch schedule of Algorithm 7.1 (M = I), the construction of
-// A^H, and the fp32-inner / fp64-refinement driver.
+// the per-cycle launch schedule of Algorithm 7.1 (M = I; the block-Jacobi M is
+// folded into A M^{-1}), in the fused order, the literal order or the
+// transpose-free form, the construction of A^H, the fp32-inner /
+// fp64-refinement driver, batched one-workgroup solves, sequences of systems
+// with the choice of n of Section 5.2, and the serving loop.
 //
 // One Engine<V> owns the Krylov workspace for one value type V (fp64 or fp32,
 // real or complex).  Every step of the iteration is a kernel from

@@ -28,6 +28,10 @@
 // pass (k_gwcomb) then forms g_k = g + sum b_s g_s and w_k = v + sum b_s w_s
 // (the recombination, the price of having no A^H) and reduces q_s^H w_k,
 // s >= i, the S column and c of step i.
+//
+// Literal order: the two recurrences can also run as written, one coefficient
+// per pass and reduction (k_lit_tilde, k_lit_beta, PH_LIT_T / PH_LIT_B), each
+// from the inner product of the vector the previous coefficient updated.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -1,10 +1,10 @@
 // Sparse matrix-vector products of the iteration (gfx950): w = A g with the
 // shadow inner products of the step fused into the epilogue, z = A u with the
 // two sums of the minimisation step, r = b - A x, and plain products.  CSR rows
-// of up to 8 entries use a wave-local kernel (k_spmv_csrw); longer rows and
-// 3x3-block (BSR3) rows use an LDS-tiled kernel (k_spmv).  Every product is
-// one pass over A and the vectors, with the sums reduced into per-workgroup
-// partials like the vector passes.
+// of up to 8 entries use a wave-local kernel (k_spmv_csrw), 3x3-block (BSR3)
+// rows of up to 8 blocks another (k_spmv_bsrw); longer rows use an LDS-tiled
+// kernel (k_spmv).  Every product is one pass over A and the vectors, with the
+// sums reduced into per-workgroup partials like the vector passes.
 #pragma once
 
 #include "mlb_kernels.hpp"
