@@ -43,6 +43,26 @@ def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False, literal=False):
     return mat + vec_avg * N * sv
 
 
+def copy_rate_gbs(torch, dev, gib=1.0, reps=5):
+    """Practical HBM ceiling: a plain elementwise copy kernel over `gib` GiB (read and written once
+    per launch; the kernel the counter calibration uses), the best of `reps` launches timed with
+    events on the current stream, in GB/s (1e9 B/s)."""
+    nel = int(gib * (1 << 30) / 8)
+    src = torch.ones(nel, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.mul(src, 1.0, out=dst)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nel * 8 / (best * 1e-3) / 1e9
+
+
 def measured_traffic(workload, root=ROOT):
     """HBM bytes per SpMV-step launch from the committed rocprofv3 counter summary, or None when
     the kernel source has changed since the counters were taken (or no summary exists)."""
@@ -367,6 +387,8 @@ def main():
     log(f"[bench] spmv-step {ms_spmv * 1e3:.1f} us/launch -> {achieved:.0f} GB/s ; alpha {ms_alpha * 1e3:.1f} us ; "
         f"combine {ms_comb * 1e3:.1f} us ; recombine {ms_recomb * 1e3:.1f} us")
     solver.close()
+    copy_gbs = copy_rate_gbs(torch, dev)
+    log(f"[bench] device copy (practical ceiling): {copy_gbs:.0f} GB/s")
     if args.calib_copy > 0:
         # a plain copy kernel of known size: reads and writes calib-copy GiB per launch
         nel = int(args.calib_copy * (1 << 30) / 8)
@@ -414,7 +436,7 @@ def main():
             "matrix_setup_ms": create_ms,
         },
         "roofline": {
-            "kernel": "k_spmv_csrw / k_spmv (SpMV step: w_i = A g_i with q_s^H w_i, s >= i)",
+            "kernel": "k_spmv_csrw / k_spmv_bsrw / k_spmv (SpMV step: w_i = A g_i with q_s^H w_i, s >= i)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
@@ -423,6 +445,8 @@ def main():
             "traffic": measured_traffic(profile_key),
             "bytes_per_launch": bytes_spmv,
             "us_per_launch": ms_spmv * 1e3,
+            "copy_ceiling": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
     }
     if not args.no_cpu:
