@@ -4,8 +4,11 @@
  * The library solves sparse A x = b with ML(n)BiCGStabt, the A^H-using
  * ML(n)BiCGStab algorithm of M.-C. Yeung, "An introduction to ML(n)BiCGStab"
  * (arXiv 1106.3678): Algorithm 4.1 (Section 4.3), in the i/j loop form of
- * Algorithm 7.1 (Section 7) with M = I.  Every iteration runs in hand-written
- * HIP kernels on one GPU; scalars and convergence control stay on the device.
+ * Algorithm 7.1 (Section 7), with M = I or the block diagonal of A.  Options
+ * select the order of its two recurrences (a fused Gram-matrix form, or the
+ * literal one) and a transpose-free form without A^H.  Every iteration runs in
+ * hand-written HIP kernels on one GPU; scalars and convergence control stay on
+ * the device.
  *
  * Conventions shared by every entry point
  *  - Array pointers named "device" point to GPU memory of the current HIP
@@ -249,9 +252,11 @@ enum {
   MLB_KERNEL_SPMV_STEP = 0,   /* SpMV + multi-dot of a step (every SpMV of a cycle
                                  but the one of the minimisation step)           */
   MLB_KERNEL_ALPHA_STEP = 1,  /* x, r update + norm + multi-dot                   */
-  MLB_KERNEL_COMBINE = 2,     /* beta~ combination + F multi-dot                  */
+  MLB_KERNEL_COMBINE = 2,     /* beta~ combination + F multi-dot (literal order:
+                                 the beta~ passes)                               */
   MLB_KERNEL_RECOMBINE = 3    /* g_k = g + sum beta_s g_s (transpose_free: also
-                                 w_k and its multi-dot)                          */
+                                 w_k and its multi-dot; literal order: the beta
+                                 passes)                                         */
 };
 
 /*
