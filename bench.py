@@ -144,7 +144,8 @@ def bench_serving(args, torch, workloads, binding):
         delay = t0 + r.arrival_s - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        tickets.append(server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec))
+        tickets.append(server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec,
+                                     transpose_free=args.transpose_free))
     lat, flags, errs, iters = [], [], [], []
     for tk in tickets:
         res, tim = server.wait(tk)
@@ -165,7 +166,8 @@ def bench_serving(args, torch, workloads, binding):
     server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight,
                             small_n_max=args.small_n_max)
     t2 = time.perf_counter()
-    tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec)
+    tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec,
+                             transpose_free=args.transpose_free)
                for r, p, dA, b, x, Q in items]
     sat_flags = [server.wait(tk)[0].flag for tk in tickets]
     saturated = time.perf_counter() - t2
@@ -195,6 +197,7 @@ def bench_serving(args, torch, workloads, binding):
                    "arrival_rate_per_s": 200.0, "N_range": [int(min(r.N for r in reqs)), int(max(r.N for r in reqs))],
                    "inflight": args.inflight, "budget_gb": args.budget_gb, "tol": 1e-10,
                    "small_n_max": args.small_n_max,
+                   "variant": "transpose-free (no A^H)" if args.transpose_free else "Algorithm 7.1 (explicit A^H)",
                    "all_converged": bool(all(f == 0 for f in flags)), "max_err_true": float(max(errs)),
                    "total_iterations": int(sum(iters))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
