@@ -232,6 +232,18 @@ int mlb_sequence_destroy(mlb_sequence_handle s);
 /* Free everything create() allocated.  NULL is accepted. */
 int mlbicgstab_destroy(mlb_handle h);
 
+/*
+ * y = A x (op = MLB_OP_A, the caller's A) or y = A^H x (op = MLB_OP_AH, the
+ * conjugate transpose the solver built for f_s = A^H q_s, Algorithm 4.1 step
+ * 2).  A transpose_free or preconditioned solver holds no A^H of A:
+ * MLB_OP_AH returns MLB_EUNSUPPORTED there.  x and y are device vectors of N
+ * values of the solver's value type (x is read, y written; they must not
+ * overlap).  Runs the library's SpMV kernel on the solver's stream and
+ * synchronises it.  For residuals and for tests of the products.
+ */
+enum { MLB_OP_A = 0, MLB_OP_AH = 1 };
+int mlbicgstab_matvec(mlb_handle h, int32_t op, const void* x, void* y);
+
 /* Message for the last API error on this thread ("" if none). */
 const char* mlbicgstab_last_error(void);
 

@@ -20,6 +20,7 @@ MLB_CSR, MLB_BSR3 = 0, 1
 MLB_PREC_FP64, MLB_PREC_FP32_IR = 0, 1
 MLB_PRECOND_NONE, MLB_PRECOND_JACOBI = 0, 1
 MLB_ORDER_FUSED, MLB_ORDER_LITERAL = 0, 1
+MLB_OP_A, MLB_OP_AH = 0, 1
 MLB_MAX_N = 32
 MLB_KERNEL_SPMV_STEP, MLB_KERNEL_ALPHA_STEP, MLB_KERNEL_COMBINE, MLB_KERNEL_RECOMBINE = 0, 1, 2, 3
 
@@ -111,6 +112,8 @@ _lib.mlbicgstab_destroy.argtypes = [mlb_handle]
 _lib.mlbicgstab_destroy.restype = ctypes.c_int
 _lib.mlbicgstab_last_error.argtypes = []
 _lib.mlbicgstab_last_error.restype = ctypes.c_char_p
+_lib.mlbicgstab_matvec.argtypes = [mlb_handle, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+_lib.mlbicgstab_matvec.restype = ctypes.c_int
 _lib.mlbicgstab_time_kernel.argtypes = [mlb_handle, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
 _lib.mlbicgstab_time_kernel.restype = ctypes.c_int
 _lib.mlbicgstab_solve_batch.argtypes = [ctypes.POINTER(mlb_handle), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
@@ -197,6 +200,10 @@ def mlbicgstab_destroy(h) -> int:
 
 def mlbicgstab_last_error() -> str:
     return _lib.mlbicgstab_last_error().decode()
+
+
+def mlbicgstab_matvec(h, op: int, x_ptr: int, y_ptr: int) -> None:
+    _check(_lib.mlbicgstab_matvec(h, op, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr)))
 
 
 def mlbicgstab_time_kernel(h, kernel: int, reps: int) -> float:
@@ -363,6 +370,13 @@ class Solver:
 
     def time_kernel(self, kernel: int, reps: int) -> float:
         return mlbicgstab_time_kernel(self.h, kernel, reps)
+
+    def matvec(self, x, y, op: int = MLB_OP_A) -> None:
+        """y = A x (op = MLB_OP_A) or y = A^H x (op = MLB_OP_AH) on the library's SpMV kernels."""
+        N = self.dmat.nrows
+        if x.numel() != N or y.numel() != N or not x.is_contiguous() or not y.is_contiguous():
+            raise ValueError("x and y must be contiguous vectors of length N")
+        mlbicgstab_matvec(self.h, op, x.data_ptr(), y.data_ptr())
 
     def close(self):
         if self.h:

@@ -425,11 +425,11 @@ struct Engine {
     launch_spmv_nd<V, Sc, SM_RESID, 4>(M, grid_spmv, s, st, part, a, phase, 0, 0, n, flags);
     if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, 4, 3, phase, 0, 0);
   }
-  void spmv_plain(const Mat<V>& M, const V* xin, V* out) {
+  void spmv_plain(const Mat<V>& M, const V* xin, V* out, int flags = 0) {
     SpmvArgs<V> a{};
     a.format = M.format; a.nrows = M.nrows; a.nbrows = M.nbrows; a.rp = M.rp; a.ci = M.ci; a.val = M.val;
     a.xin = xin; a.out1 = out;
-    launch_spmv_nd<V, Sc, SM_PLAIN, 4>(M, grid_spmv, s, st, part, a, PH_NONE, 0, 0, n, 0);
+    launch_spmv_nd<V, Sc, SM_PLAIN, 4>(M, grid_spmv, s, st, part, a, PH_NONE, 0, 0, n, flags);
   }
   void spmv_omega(const V* u, V* zout) {
     SpmvArgs<V> a{};
@@ -1040,6 +1040,15 @@ static double time_kernel_impl(Engine<V>& e, int kernel, int reps) {
   return pairs ? total / pairs : 0.0;
 }
 
+// y = A x with the caller's A, or y = A^H x with the solver's conjugate transpose,
+// on the solver's stream (whatever the done flag of the last solve says).
+template <class V64, class V32>
+static void matvec_impl(mlb_solver* h, Impl<V64, V32>& im, int op, const V64* x, V64* y) {
+  im.e64.spmv_plain(op == MLB_OP_A ? im.A0 : im.e64.AH, x, y, F_IGNORE_DONE);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(h->s));
+}
+
 template <class F>
 static int guarded(F&& f) {
   try {
@@ -1380,6 +1389,20 @@ int mlb_sequence_destroy(mlb_sequence_handle q) {
     if (!q) return 0;
     (void)hipStreamSynchronize(q->h->s);
     delete q;
+    return 0;
+  });
+}
+
+int mlbicgstab_matvec(mlb_handle h, int32_t op, const void* x, void* y) {
+  return guarded([&]() -> int {
+    if (!h || !x || !y) throw Error{MLB_EINVAL, "handle, x and y must be non-NULL"};
+    if (op != MLB_OP_A && op != MLB_OP_AH) throw Error{MLB_EINVAL, "op must be MLB_OP_A or MLB_OP_AH"};
+    if (op == MLB_OP_AH && (h->opt.transpose_free || h->opt.precond != MLB_PRECOND_NONE))
+      throw Error{MLB_EUNSUPPORTED, "A^H is held only without transpose_free and without a preconditioner"};
+    if (h->real)
+      matvec_impl(h, *h->real, op, (const double*)x, (double*)y);
+    else
+      matvec_impl(h, *h->cpx, op, (const cplx<double>*)x, (cplx<double>*)y);
     return 0;
   });
 }

@@ -95,6 +95,7 @@ def test_null_handle_paths(binding):
     assert binding.raw_call("mlbicgstab_destroy", None) == 0
     ms = ctypes.c_double()
     assert binding.raw_call("mlbicgstab_time_kernel", None, 0, 1, ctypes.byref(ms)) == binding.MLB_EINVAL
+    assert binding.raw_call("mlbicgstab_matvec", None, binding.MLB_OP_A, None, None) == binding.MLB_EINVAL
     # batched solves: NULL arrays and an empty batch are refused before anything runs
     assert binding.raw_call("mlbicgstab_solve_batch", None, 1, None, None, None, None, None) == binding.MLB_EINVAL
     hs = (binding.mlb_handle * 1)()

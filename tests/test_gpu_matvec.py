@@ -1,0 +1,150 @@
+"""The library's sparse products on their own (mlbicgstab_matvec) against scipy in fp64.
+
+y = A x is the product every step of Algorithm 7.1 forms; y = A^H x is the one that builds
+f_s = A^H q_s (Algorithm 4.1, step 2).  Both are plain definitions, so the reference is
+scipy's CSR product.  Bar, element by element: |y_i - ref_i| <= 4 k_i u (|A| |x|)_i with k_i
+the stored entries of row i and u = 2^-53 (the error bound of a length-k dot product).
+Cases cover every SpMV kernel the library picks: wave-local CSR (up to 8 entries a row),
+the LDS tile (longer rows), wave-local 3x3 blocks, complex values, ragged sizes, a
+solver before and after a solve, and the 128^3 operator of the benchmark.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads
+from tests.gpu_util import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import torch  # noqa: E402
+
+from paper_1106_3678_amd import binding  # noqa: E402
+
+U = 2.0 ** -53
+
+
+def _vec(N, seed, cplx):
+    g = np.random.default_rng(seed)
+    v = g.standard_normal(N)
+    return v + 1j * g.standard_normal(N) if cplx else v
+
+
+def _check(A, y, x):
+    A = sp.csr_matrix(A)
+    ref = A @ x
+    mag = abs(A) @ np.abs(x)
+    k = np.diff(A.indptr)
+    bound = 4 * np.maximum(k, 1) * U * mag + 1e-300
+    err = np.abs(y - ref)
+    worst = float(np.max(err / bound)) if len(err) else 0.0
+    assert worst <= 1.0, worst
+    return worst
+
+
+def _solver(A, n=4, **kw):
+    dA = binding.to_device(A)
+    return dA, binding.Solver(dA, n, tol=1e-10, maxit=100, **kw)
+
+
+def _apply(s, x, op):
+    dx = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    dy = torch.full_like(dx, float("nan"))
+    s.matvec(dx, dy, op)
+    return dy.cpu().numpy()
+
+
+def _long_rows(N, per_row, seed):
+    g = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(N), per_row)
+    cols = g.integers(0, N, N * per_row)
+    A = sp.csr_matrix((g.standard_normal(N * per_row), (rows, cols)), shape=(N, N))
+    A.sum_duplicates()
+    return A + sp.identity(N, format="csr") * per_row
+
+
+CASES = {
+    "convdiff2d_33": lambda: workloads.config1(n=4, m=33).A,
+    "convdiff3d_16": lambda: workloads.config2(n=4, m=16).A,
+    "long_rows_40": lambda: _long_rows(3001, 40, 1),
+    "reservoir_8x10x6": lambda: workloads.config3(n=4, grid=(8, 10, 6)).A,
+    "helmholtz_10": lambda: workloads.config5(n=4, m=10).A,
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_A_and_AH(case):
+    A = CASES[case]()
+    cplx = np.iscomplexobj(A.data)
+    N = A.shape[0]
+    dA, s = _solver(A)
+    try:
+        for op, M in ((binding.MLB_OP_A, A), (binding.MLB_OP_AH, A.conj().T)):
+            x = _vec(N, 7 + op, cplx)
+            w = _check(M, _apply(s, x, op), x)
+            print(f"{case} op={op}: N={N} worst error / bound {w:.2e}", flush=True)
+    finally:
+        s.close()
+
+
+def test_after_a_solve_and_repeated():
+    """A finished solve leaves its done flag set; the product still runs, and reruns are bitwise."""
+    p = workloads.config1(n=4, m=32)
+    dA, s = _solver(p.A)
+    try:
+        x0 = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+        assert s.solve(torch.from_numpy(p.b).cuda(), x0, binding.column_major(p.Q)).flag == 0
+        x = _vec(p.N, 3, False)
+        y1 = _apply(s, x, binding.MLB_OP_A)
+        y2 = _apply(s, x, binding.MLB_OP_A)
+        _check(p.A, y1, x)
+        assert np.array_equal(y1, y2)
+        # the product of the solution is b up to the converged residual
+        r = p.b - _apply(s, x0.cpu().numpy(), binding.MLB_OP_A)
+        assert np.linalg.norm(r) / np.linalg.norm(p.b) < 1e-9
+    finally:
+        s.close()
+
+
+def test_preconditioned_and_transpose_free_solvers():
+    """op A is the caller's A in every mode; A^H is held only by the plain iteration."""
+    A = workloads.config3(n=4, grid=(8, 10, 6)).A
+    x = _vec(A.shape[0], 5, False)
+    for kw in ({"precond": binding.MLB_PRECOND_JACOBI}, {"transpose_free": True}):
+        dA, s = _solver(A, **kw)
+        try:
+            _check(A, _apply(s, x, binding.MLB_OP_A), x)
+            with pytest.raises(binding.MlbError) as e:
+                _apply(s, x, binding.MLB_OP_AH)
+            assert e.value.code == binding.MLB_EUNSUPPORTED
+        finally:
+            s.close()
+
+
+def test_bad_op_and_shapes():
+    A = workloads.config1(n=4, m=8).A
+    dA, s = _solver(A)
+    try:
+        x = torch.zeros(A.shape[0], dtype=torch.float64, device="cuda")
+        with pytest.raises(binding.MlbError) as e:
+            s.matvec(x, torch.empty_like(x), 2)
+        assert e.value.code == binding.MLB_EINVAL
+        with pytest.raises(ValueError):
+            s.matvec(x[:-1], torch.empty_like(x))
+    finally:
+        s.close()
+
+
+def test_full_size_convdiff3d():
+    """The 128^3 operator (N = 2,097,152) of the benchmark, both products."""
+    A = workloads.config2(n=4, m=128).A
+    dA, s = _solver(A)
+    try:
+        for op, M in ((binding.MLB_OP_A, A), (binding.MLB_OP_AH, A.T)):
+            x = _vec(A.shape[0], 11, False)
+            print(f"128^3 op={op}: worst error / bound {_check(M, _apply(s, x, op), x):.2e}", flush=True)
+    finally:
+        s.close()
