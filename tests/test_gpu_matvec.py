@@ -6,7 +6,8 @@ scipy's CSR product.  Bar, element by element: |y_i - ref_i| <= 4 k_i u (|A| |x|
 the stored entries of row i and u = 2^-53 (the error bound of a length-k dot product).
 Cases cover every SpMV kernel the library picks: wave-local CSR (up to 8 entries a row),
 the LDS tile (longer rows), wave-local 3x3 blocks, complex values, ragged sizes, a
-solver before and after a solve, and the 128^3 operator of the benchmark.
+solver before and after a solve, an A with no entries, N = 1, and the 128^3 operator of the
+benchmark.
 """
 import numpy as np
 import pytest
@@ -146,5 +147,26 @@ def test_full_size_convdiff3d():
         for op, M in ((binding.MLB_OP_A, A), (binding.MLB_OP_AH, A.T)):
             x = _vec(A.shape[0], 11, False)
             print(f"128^3 op={op}: worst error / bound {_check(M, _apply(s, x, op), x):.2e}", flush=True)
+    finally:
+        s.close()
+
+
+def test_no_entries_and_one_row():
+    """An A with empty index and value arrays gives y = 0 exactly; N = 1 gives the one product."""
+    Z = sp.csr_matrix((3, 3))
+    assert Z.nnz == 0
+    dA, s = _solver(Z, n=2)
+    try:
+        for op in (binding.MLB_OP_A, binding.MLB_OP_AH):
+            y = _apply(s, _vec(3, 1, False), op)
+            assert np.array_equal(y, np.zeros(3))
+    finally:
+        s.close()
+    one = sp.csr_matrix(np.array([[2.5 - 1.5j]]))
+    dA, s = _solver(one, n=1)
+    try:
+        x = np.array([0.75 + 2.0j])
+        assert _apply(s, x, binding.MLB_OP_A)[0] == (2.5 - 1.5j) * x[0]
+        assert _apply(s, x, binding.MLB_OP_AH)[0] == (2.5 + 1.5j) * x[0]
     finally:
         s.close()
