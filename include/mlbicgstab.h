@@ -62,7 +62,11 @@ enum { MLB_PRECOND_NONE = 0, MLB_PRECOND_JACOBI = 1 };
  *         blocks; row_ptr[nrows/3+1] and col_idx[nnz] index blocks; values
  *         holds nnz blocks of 9 entries each, row-major inside a block.
  * Indices are 0-based int32; row_ptr[0] must be 0 and row_ptr[last] = nnz.
+ * nrows and nnz are at most MLB_MAX_INDEX (2^31 - 2^20): the kernels index
+ * rows and entries with 32-bit integers and step through them in strides of
+ * up to 2^20, which must not overflow.  Larger values return MLB_EINVAL.
  */
+#define MLB_MAX_INDEX 2146435072LL
 typedef struct {
   int32_t format;           /* MLB_CSR or MLB_BSR3                             */
   int32_t dtype;            /* MLB_R64 or MLB_C128                             */

@@ -22,6 +22,7 @@ MLB_PRECOND_NONE, MLB_PRECOND_JACOBI = 0, 1
 MLB_ORDER_FUSED, MLB_ORDER_LITERAL = 0, 1
 MLB_OP_A, MLB_OP_AH = 0, 1
 MLB_MAX_N = 32
+MLB_MAX_INDEX = 2 ** 31 - 2 ** 20   # largest nrows and nnz
 MLB_KERNEL_SPMV_STEP, MLB_KERNEL_ALPHA_STEP, MLB_KERNEL_COMBINE, MLB_KERNEL_RECOMBINE = 0, 1, 2, 3
 
 

@@ -767,9 +767,11 @@ static void check_matrix(const mlb_matrix* A) {
   if (!A) throw Error{MLB_EINVAL, "matrix pointer is NULL"};
   if (A->format != MLB_CSR && A->format != MLB_BSR3) throw Error{MLB_EINVAL, "format must be MLB_CSR or MLB_BSR3"};
   if (A->dtype != MLB_R64 && A->dtype != MLB_C128) throw Error{MLB_EINVAL, "dtype must be MLB_R64 or MLB_C128"};
-  if (A->nrows < 1 || A->nrows > 0x7fffffffLL) throw Error{MLB_EINVAL, "nrows must be in [1, 2^31)"};
+  // 32-bit row and entry indices advance by grid strides of up to 4096 * BLOCK
+  static_assert(4096LL * BLOCK + MLB_MAX_INDEX <= 0x7fffffffLL + 1, "index headroom below 2^31");
+  if (A->nrows < 1 || A->nrows > MLB_MAX_INDEX) throw Error{MLB_EINVAL, "nrows must be in [1, 2^31 - 2^20]"};
   if (A->format == MLB_BSR3 && A->nrows % 3 != 0) throw Error{MLB_EINVAL, "BSR3 needs nrows divisible by 3"};
-  if (A->nnz < 0 || A->nnz > 0x7fffffffLL) throw Error{MLB_EINVAL, "nnz must be in [0, 2^31)"};
+  if (A->nnz < 0 || A->nnz > MLB_MAX_INDEX) throw Error{MLB_EINVAL, "nnz must be in [0, 2^31 - 2^20]"};
   if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values)))
     throw Error{MLB_EINVAL, "row_ptr, col_idx and values must be device pointers"};
 }

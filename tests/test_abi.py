@@ -58,6 +58,8 @@ def _opt(binding, **kw):
 @pytest.mark.parametrize("bad", [
     dict(m=dict(format=7)), dict(m=dict(dtype=9)), dict(m=dict(nrows=0)), dict(m=dict(nrows=10, format=1)),
     dict(m=dict(nnz=-1)), dict(m=dict(row_ptr=None)),
+    dict(m=dict(nrows=2 ** 31 - 2 ** 20 + 1)), dict(m=dict(nrows=2 ** 31 - 1)),
+    dict(m=dict(nnz=2 ** 31 - 2 ** 20 + 1)), dict(m=dict(nrows=3 * 2 ** 30, format=1)),
     dict(o=dict(n=0)), dict(o=dict(tol=0.0)), dict(o=dict(tol=float("nan"))), dict(o=dict(maxit=0)),
     dict(o=dict(kappa=-1.0)), dict(o=dict(precision=5)), dict(o=dict(record_iterates=3)),
     dict(o=dict(precond=7)), dict(o=dict(transpose_free=2)), dict(o=dict(order=5)),
