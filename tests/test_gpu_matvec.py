@@ -170,3 +170,19 @@ def test_no_entries_and_one_row():
         assert _apply(s, x, binding.MLB_OP_AH)[0] == (2.5 + 1.5j) * x[0]
     finally:
         s.close()
+
+
+def test_fp32_refinement_solver_uses_fp64_products():
+    """An fp32-IR solver iterates on an fp32 copy; its products are the fp64 ones, bitwise."""
+    p = workloads.config2(n=4, m=16)
+    x = _vec(p.N, 9, False)
+    ys = []
+    for prec in (binding.MLB_PREC_FP64, binding.MLB_PREC_FP32_IR):
+        dA, s = _solver(p.A, precision=prec)
+        try:
+            ys.append([_apply(s, x, op) for op in (binding.MLB_OP_A, binding.MLB_OP_AH)])
+        finally:
+            s.close()
+    _check(p.A, ys[1][0], x)
+    _check(p.A.T, ys[1][1], x)
+    assert np.array_equal(ys[0][0], ys[1][0]) and np.array_equal(ys[0][1], ys[1][1])
