@@ -5,7 +5,8 @@ f_s = A^H q_s (Algorithm 4.1, step 2).  Both are plain definitions, so the refer
 scipy's CSR product.  Bar, element by element: |y_i - ref_i| <= 4 k_i u (|A| |x|)_i with k_i
 the stored entries of row i and u = 2^-53 (the error bound of a length-k dot product).
 Cases cover every SpMV kernel the library picks: wave-local CSR (up to 8 entries a row),
-the LDS tile (longer rows), wave-local 3x3 blocks, complex values, ragged sizes, a
+the LDS tile (longer rows), wave-local 3x3 blocks (4 and 8 lanes a block row), the LDS tile
+for 3x3 blocks (12 and 24 blocks a row), complex values, ragged sizes, a
 solver before and after a solve, an A with no entries, N = 1, and the 128^3 operator of the
 benchmark.
 """
@@ -67,7 +68,24 @@ def _long_rows(N, per_row, seed):
     return A + sp.identity(N, format="csr") * per_row
 
 
+def _bsr3(nb, per_row, seed, cplx=False):
+    """3x3 blocks: the diagonal plus per_row random blocks a block row."""
+    g = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(nb), per_row)
+    P = sp.csr_matrix((np.ones(nb * per_row), (rows, g.integers(0, nb, nb * per_row))), shape=(nb, nb))
+    P = (P + sp.identity(nb, format="csr")).tocsr()
+    P.sum_duplicates()
+    P.sort_indices()
+    data = g.standard_normal((P.nnz, 3, 3))
+    if cplx:
+        data = data + 1j * g.standard_normal((P.nnz, 3, 3))
+    return sp.bsr_matrix((data, P.indices, P.indptr), shape=(3 * nb, 3 * nb))
+
+
 CASES = {
+    "bsr3_2_blocks_a_row": lambda: _bsr3(1001, 1, 2),
+    "bsr3_12_blocks_a_row": lambda: _bsr3(1001, 11, 3),
+    "bsr3_24_blocks_a_row_complex": lambda: _bsr3(517, 23, 4, cplx=True),
     "convdiff2d_33": lambda: workloads.config1(n=4, m=33).A,
     "convdiff3d_16": lambda: workloads.config2(n=4, m=16).A,
     "long_rows_40": lambda: _long_rows(3001, 40, 1),
