@@ -44,6 +44,40 @@ def check_parity(p, K=20, x_tol=1e-6, sensitive=False, precond=0, n_perturb=1):
     return res, o
 
 
+def _bsr3_dd(nb, per_row, seed, cplx=False):
+    """A diagonally dominant 3x3-block system: per block row the diagonal block
+    3 (per_row + 1) I plus noise, and per_row random off-diagonal blocks."""
+    g = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(nb), per_row)
+    P = sp.csr_matrix((np.ones(nb * per_row), (rows, g.integers(0, nb, nb * per_row))), shape=(nb, nb))
+    P = (P + sp.identity(nb, format="csr")).tocsr()
+    P.sum_duplicates()
+    P.sort_indices()
+    data = 0.5 * g.standard_normal((P.nnz, 3, 3))
+    if cplx:
+        data = data + 0.5j * g.standard_normal((P.nnz, 3, 3))
+    on_diag = P.indices == np.repeat(np.arange(nb), np.diff(P.indptr))
+    data[on_diag] += 3.0 * (per_row + 1) * np.eye(3)
+    return sp.bsr_matrix((data, P.indices, P.indptr), shape=(3 * nb, 3 * nb))
+
+
+@pytest.mark.parametrize("per_row,cplx", [(1, False), (11, False), (23, True)])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_bsr3_lane_variants(per_row, cplx, precond):
+    """Block rows of 2, 12 and 24 blocks: the 4-lane wave kernel and the 16- and 32-lane
+    tile kernels for 3x3 blocks, in every epilogue of a solve."""
+    nb = 1001 if per_row < 20 else 517
+    A = _bsr3_dd(nb, per_row, 40 + per_row, cplx)
+    N = A.shape[0]
+    g = np.random.default_rng(7)
+    b = g.standard_normal(N) + (1j * g.standard_normal(N) if cplx else 0.0)
+    Q = g.standard_normal((N, 4)) + (1j * g.standard_normal((N, 4)) if cplx else 0.0)
+    p = workloads.Problem(f"bsr3_{per_row + 1}_blocks", A, b, np.asfortranarray(Q), np.zeros(N, dtype=b.dtype),
+                          4, 1e-10, 500)
+    res, o = check_parity(p, precond=precond)
+    assert res.flag == 0
+
+
 @pytest.mark.parametrize("n", [1, 2, 4, 8])
 def test_convdiff2d_32(n):
     """2D convection-diffusion on a 32 x 32 grid (N = 1024, several tiles)."""
