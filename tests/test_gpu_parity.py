@@ -16,6 +16,8 @@ pytestmark = pytest.mark.gpu
 if not gpu_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
+from paper_1106_3678_amd import binding  # noqa: E402
+
 
 def check_parity(p, K=20, x_tol=1e-6, sensitive=False, precond=0, n_perturb=1):
     """Strict bars; with sensitive=True each bar is widened to what the oracle's own
@@ -76,6 +78,42 @@ def test_bsr3_lane_variants(per_row, cplx, precond):
                           4, 1e-10, 500)
     res, o = check_parity(p, precond=precond)
     assert res.flag == 0
+    check_fp32_refinement(p, o, precond)
+
+
+def check_fp32_refinement(p, o, precond):
+    """The fp32 copies of the same kernels inside fp64 refinement: converged, x near the oracle's."""
+    res, x, _ = run_gpu(p, precision=binding.MLB_PREC_FP32_IR, precond=precond)
+    print(f"  fp32-IR: flag={res.flag} iter={res.iter} true={res.err_true:.3e}", flush=True)
+    assert res.flag == 0 and res.err_true < p.tol
+    assert rel(x, o.x) < 1e-6
+
+
+def _csr_dd(N, per_row, seed, cplx=False):
+    """A diagonally dominant CSR system with per_row random off-diagonal entries a row."""
+    g = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(N), per_row)
+    vals = g.standard_normal(N * per_row) + (1j * g.standard_normal(N * per_row) if cplx else 0.0)
+    A = sp.csr_matrix((vals, (rows, g.integers(0, N, N * per_row))), shape=(N, N))
+    A = (A + sp.identity(N, format="csr") * (2.0 * per_row)).tocsr()
+    A.sum_duplicates()
+    return A
+
+
+@pytest.mark.parametrize("per_row,cplx", [(11, False), (40, True)])
+def test_csr_long_rows(per_row, cplx):
+    """Rows of about 12 and 41 entries (the second complex): the 16- and 32-lane tile kernels
+    in every epilogue of a solve, then their fp32 copies inside fp64 refinement."""
+    N = 2003
+    A = _csr_dd(N, per_row, 60 + per_row, cplx)
+    g = np.random.default_rng(8)
+    b = g.standard_normal(N) + (1j * g.standard_normal(N) if cplx else 0.0)
+    Q = g.standard_normal((N, 4)) + (1j * g.standard_normal((N, 4)) if cplx else 0.0)
+    p = workloads.Problem(f"csr_{per_row + 1}_entries", A, b, np.asfortranarray(Q), np.zeros(N, dtype=b.dtype),
+                          4, 1e-10, 500)
+    res, o = check_parity(p)
+    assert res.flag == 0
+    check_fp32_refinement(p, o, 0)
 
 
 @pytest.mark.parametrize("n", [1, 2, 4, 8])
