@@ -82,11 +82,24 @@ def test_bsr3_lane_variants(per_row, cplx, precond):
 
 
 def check_fp32_refinement(p, o, precond):
-    """The fp32 copies of the same kernels inside fp64 refinement: converged, x near the oracle's."""
+    """The fp32 copies of the same kernels inside fp64 refinement: converged, x near the oracle's.
+    Then the literal recurrence order and the transpose-free iteration on the same kernels, each
+    against the oracle's run of the same iteration: same flag, iteration counts within 5% (at
+    least 1), x within 1e-6."""
     res, x, _ = run_gpu(p, precision=binding.MLB_PREC_FP32_IR, precond=precond)
     print(f"  fp32-IR: flag={res.flag} iter={res.iter} true={res.err_true:.3e}", flush=True)
     assert res.flag == 0 and res.err_true < p.tol
     assert rel(x, o.x) < 1e-6
+    res, x, _ = run_gpu(p, precond=precond, order=binding.MLB_ORDER_LITERAL)
+    print(f"  literal: flag={res.flag} iter={res.iter} true={res.err_true:.3e}", flush=True)
+    assert res.flag == o.flag and abs(res.iter - o.iter) <= max(1, int(0.05 * o.iter))
+    assert rel(x, o.x) < 1e-6
+    ot = run_oracle(p, precond=precond, transpose_free=True)
+    res, x, _ = run_gpu(p, precond=precond, transpose_free=True)
+    print(f"  transpose-free: flag={res.flag} iter={res.iter} true={res.err_true:.3e} | oracle iter={ot.iter}",
+          flush=True)
+    assert res.flag == ot.flag == 0 and abs(res.iter - ot.iter) <= max(1, int(0.05 * ot.iter))
+    assert rel(x, ot.x) < 1e-6
 
 
 def _csr_dd(N, per_row, seed, cplx=False):
