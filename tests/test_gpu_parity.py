@@ -116,7 +116,8 @@ def _csr_dd(N, per_row, seed, cplx=False):
 @pytest.mark.parametrize("per_row,cplx", [(11, False), (40, True)])
 def test_csr_long_rows(per_row, cplx):
     """Rows of about 12 and 41 entries (the second complex): the 16- and 32-lane tile kernels
-    in every epilogue of a solve, then their fp32 copies inside fp64 refinement."""
+    in every epilogue of a solve, then their fp32 copies inside fp64 refinement, and the batch
+    kernel on the same systems."""
     N = 2003
     A = _csr_dd(N, per_row, 60 + per_row, cplx)
     g = np.random.default_rng(8)
@@ -127,6 +128,25 @@ def test_csr_long_rows(per_row, cplx):
     res, o = check_parity(p)
     assert res.flag == 0
     check_fp32_refinement(p, o, 0)
+    # the one-workgroup batch kernel (its own row loop) on the same system, both iterations
+    import torch
+
+    dA = binding.to_device(p.A)
+    dt = torch.complex128 if cplx else torch.float64
+    db = torch.from_numpy(p.b.astype(np.complex128 if cplx else np.float64)).cuda()
+    dQ = binding.column_major(p.Q)
+    for tf in (False, True):
+        oref = run_oracle(p, transpose_free=tf)
+        s = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, transpose_free=tf)
+        x = torch.zeros(N, dtype=dt, device="cuda")
+        try:
+            (rb,) = binding.solve_batch([s], [db], [x], [dQ])
+            torch.cuda.synchronize()
+        finally:
+            s.close()
+        print(f"  batch (transpose_free={tf}): flag={rb.flag} iter={rb.iter} | oracle iter={oref.iter}", flush=True)
+        assert rb.flag == oref.flag == 0 and abs(rb.iter - oref.iter) <= max(1, int(0.05 * oref.iter))
+        assert rel(x.cpu().numpy(), oref.x) < 1e-6
 
 
 @pytest.mark.parametrize("n", [1, 2, 4, 8])
