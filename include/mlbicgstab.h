@@ -242,8 +242,11 @@ int mlbicgstab_destroy(mlb_handle h);
  * 2).  A transpose_free or preconditioned solver holds no A^H of A:
  * MLB_OP_AH returns MLB_EUNSUPPORTED there.  x and y are device vectors of N
  * values of the solver's value type (x is read, y written; they must not
- * overlap).  Runs the library's SpMV kernel on the solver's stream and
- * synchronises it.  For residuals and for tests of the products.
+ * overlap; both are borrowed for the call).  Runs the library's SpMV kernel on
+ * the solver's stream and synchronises it; it reads and writes no solver state,
+ * so it may come before, between or after solves.  For residuals and for tests
+ * of the products.  Returns 0; MLB_EINVAL for a NULL handle, x or y or an
+ * unknown op; MLB_EUNSUPPORTED as above; MLB_EHIP if the launch fails.
  */
 enum { MLB_OP_A = 0, MLB_OP_AH = 1 };
 int mlbicgstab_matvec(mlb_handle h, int32_t op, const void* x, void* y);
