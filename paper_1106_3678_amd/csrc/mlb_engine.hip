@@ -330,7 +330,7 @@ struct Engine {
   }
   // Active number of shadow vectors (<= the n the workspace was sized for).  The
   // grids: one resident round of workgroups, CUs x the SpMV-step kernel's
-  // occupancy for the SpMV passes (no partly filled second round), 4 or 8 per
+  // occupancy for the SpMV passes (no partly filled second round), 4 or 6 per
   // CU for the streaming vector passes; MLB_MAX_GRID caps both.
   void set_n(int n_) {
     n = n_;
@@ -344,10 +344,11 @@ struct Engine {
       case 16: occ = launch_spmv_nd<V, Sc, SM_STEP, 16>(A, 0, s, st, nullptr, probe, 0, 0, 0, n, 0); break;
       default: occ = launch_spmv_nd<V, Sc, SM_STEP, 32>(A, 0, s, st, nullptr, probe, 0, 0, 0, n, 0); break;
     }
-    // Complex values and 16 or more shadow vectors: 4 workgroups per CU, each
-    // taking twice the rows (4-5% faster solves on 128^3 real n = 16 and 96^3
-    // complex n = 4, 8, 16); real values with n <= 8 keep 8 (4 is 1.4-2.6% slower).
-    const int vec_per_cu = traits<V>::is_complex || nb >= 16 ? 4 : 8;
+    // Complex values and 16 or more shadow vectors: 4 workgroups per CU (4-5%
+    // faster solves than 8 on 128^3 real n = 16 and 96^3 complex n = 4, 8, 16);
+    // real values with n <= 8: 6 (2-3% faster than 8 on 128^3 n = 4, 8 and the
+    // reservoir system, where 4 is 1.4-2.6% slower than 8).
+    const int vec_per_cu = traits<V>::is_complex || nb >= 16 ? 4 : 6;
     grid_vec = grid_for(N, std::min(MAX_GRID, vec_per_cu * cus));
     grid_spmv = grid_for(A.nbrows, std::min(MAX_GRID, occ * cus));
     // The LDS-tile SpMV (rows of more than 8 entries or blocks) takes 256-row
