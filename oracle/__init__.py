@@ -8,16 +8,18 @@ does, and the two share no code.
 
 Modules:
   index      -- the index functions g_n, r_n (Section 2, Table 2.1)
-  mlbicgstabt-- ML(n)BiCGStabt, Algorithm 7.1 (preconditioned form of
-                Algorithm 4.1) in its i/j loop form; M = I unless given
+  mlbicgstabt-- ML(n)BiCGStabt: Algorithm 4.1 as one loop over k, with the
+                preconditioner of Algorithm 7.1 and the omega guard of
+                eq. (5.1); M = I unless given
   mlbicg     -- ML(n)BiCG, Algorithm 3.1 (only used to pin the oracle)
-  iterative_refinement -- fp64 refinement around a lower-precision inner solve
-                (an addition of this library, not in the paper)
 
 Parity status: every function is pinned by a CPU test (Table 2.1, n=1 equals
-BiCGStab, finite termination against LU, FOM/GMRES relations, Algorithm 3.1
-and eq. (4.1), Table 4.3 operation counts) except the paper's sample execution
-(Section 7), which prints no outputs: parity unpinned.
+BiCGStab, n=1 with the kappa guard equals the guarded BiCGStab of Sleijpen and
+van der Vorst, the preconditioned iteration equals the iteration on A M^{-1}
+(Section 4.3), finite termination against LU, FOM/GMRES relations,
+Algorithm 3.1 and eq. (4.1), Table 4.3 operation counts) except the paper's
+sample execution (Section 7), which prints no outputs: parity unpinned for
+that case only.
 """
 from .index import g_n, r_n
 from .mlbicgstabt import OpCounter, Result, mlbicgstabt, true_error

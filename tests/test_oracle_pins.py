@@ -228,19 +228,124 @@ def test_biorthogonality(n):
 
     def obs(event, **st):
         Qm = st["Q"]
+        i = st["k"] % n            # k = jn + i; i = 0 at a cycle end
         if event == "w":
-            i = st["col"]
-            w = st["W"][:, i]
+            w = st["w"]
             for s in range(i):
                 worst.append(abs(np.vdot(Qm[:, s], w)) / (np.linalg.norm(Qm[:, s]) * np.linalg.norm(w)))
         else:
-            i = st["col"]
             zw = st["zw"]
             for s in range(i, n):
                 worst.append(abs(np.vdot(Qm[:, s], zw)) / (np.linalg.norm(Qm[:, s]) * np.linalg.norm(zw)))
 
     mlbicgstabt(A, vec(N, 4), Q, tol=1e-300, maxit=3 * n, observer=obs)
     assert worst and max(worst) < 1e-10
+
+
+# --------------------------------------------------------------------------- eq. (5.1): the kappa guard
+
+
+def skew_dominated(N, t, seed, complex_=False):
+    """I + t S + a small perturbation, S skew-Hermitian: well conditioned, and the cosine between
+    A s and s is about 1 / sqrt(1 + t^2 ||S||^2), so a larger t makes the kappa guard fire more."""
+    g = np.random.default_rng(seed)
+    S = g.standard_normal((N, N))
+    if complex_:
+        S = S + 1j * g.standard_normal((N, N))
+    S = (S - S.conj().T) / np.sqrt(N)
+    return np.eye(N) + t * S + 0.2 * g.standard_normal((N, N)) / np.sqrt(N)
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+@pytest.mark.parametrize("t", [0.5, 2.0])
+def test_kappa_guard_n1_equals_guarded_bicgstab(t, complex_):
+    """eq. (5.1) with kappa = 0.7 (Section 5.3): with one shadow vector the iteration is BiCGStab with
+    the Sleijpen-van der Vorst omega, written independently in tests/textbook.py.
+
+    Over the first 10 iterations the omegas and the iterates agree to 1e-8, and the guard fires on
+    some of those steps (t = 0.5: some but not all).  Past that the comparison stops meaning much:
+    on these skew-dominated systems BiCGStab's residual jumps around, and the two codes' different
+    rounding grows by up to about 5x per step (measured: 1e-15 at k = 2, 1e-9 at k = 11, 1e-3 at
+    k = 15 for t = 2).  Both still converge, with iteration counts within 5%."""
+    N = 40
+    A = skew_dominated(N, t, 11, complex_)
+    b, q = vec(N, 12, complex_), vec(N, 13, complex_)
+    kappa = 0.7
+    res = mlbicgstabt(A, b, q[:, None], tol=1e-12, maxit=300, kappa=kappa, record_x=300)
+    xs, it, flag, omegas, fired = textbook.bicgstab_guarded(A, b, q, kappa, tol=1e-12, maxit=300)
+    assert res.flag == flag == 0
+    assert abs(res.iter - it) <= max(1, 0.05 * it)
+    K = 10
+    for k in range(K):
+        assert abs(res.omegas[k] - omegas[k]) <= 1e-8 * abs(omegas[k]), k + 1
+        assert np.linalg.norm(res.x_history[k] - xs[k]) <= 1e-8 * np.linalg.norm(xs[k]), k + 1
+    assert any(fired[:K])
+    if t < 1:
+        assert not all(fired[:K])
+    assert true_error(A, res.x, b) < 1e-11
+
+
+def test_kappa_guard_first_omega_exact_ratio():
+    """Before any history differs, the guarded omega_1 is the plain omega_1 times kappa / |rho_1|, with
+    rho_1 = (A u)^H u / (||A u|| ||u||) computed here from u_1 = r_0 - alpha_1 A r_0 (eq. (5.1))."""
+    N = 30
+    A = skew_dominated(N, 2.0, 21)
+    b, q = vec(N, 22), vec(N, 23)
+    r0 = b.copy()
+    w0 = A @ r0
+    alpha = np.vdot(q, r0) / np.vdot(q, w0)
+    u = r0 - alpha * w0
+    z = A @ u
+    rho = np.vdot(z, u) / (np.linalg.norm(z) * np.linalg.norm(u))
+    assert abs(rho) < 0.7
+    plain = mlbicgstabt(A, b, q[:, None], tol=1e-12, maxit=1)
+    guarded = mlbicgstabt(A, b, q[:, None], tol=1e-12, maxit=1, kappa=0.7)
+    assert abs(guarded.omegas[0] - plain.omegas[0] * 0.7 / abs(rho)) <= 1e-12 * abs(guarded.omegas[0])
+    # kappa below |rho|: no change at all
+    same = mlbicgstabt(A, b, q[:, None], tol=1e-12, maxit=1, kappa=0.5 * abs(rho))
+    assert same.omegas[0] == plain.omegas[0]
+
+
+# --------------------------------------------------------------------------- Section 4.3: preconditioning
+
+
+def right_preconditioned_pair(N, seed, complex_=False):
+    """A diagonally dominant A and a non-diagonal, well-conditioned M (dense, tiny)."""
+    g = np.random.default_rng(seed)
+    A = dd_dense(N, seed, complex_)
+    M = np.eye(N) + 0.3 * g.standard_normal((N, N)) / np.sqrt(N)
+    if complex_:
+        M = M + 0.3j * g.standard_normal((N, N)) / np.sqrt(N)
+    return A, M
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+@pytest.mark.parametrize("n,kappa", [(1, 0.0), (3, 0.0), (4, 0.7), (5, 0.0)])
+def test_preconditioned_equals_iteration_on_A_Minv(n, kappa, complex_):
+    """Section 4.3: the preconditioned algorithm is Algorithm 4.1 applied to A M^{-1} y = b, with
+    x = M^{-1} y.  The oracle with M (f_s = M^{-H} A^H q_s, x += alpha hat g and omega hat u) is compared
+    with the oracle without M on the explicit matrix A M^{-1} from y_0 = M x_0: same flag and iteration
+    count, and x_k = M^{-1} y_k to rounding for every recorded k (three cycles and more)."""
+    N = 12
+    A, M = right_preconditioned_pair(N, 31 + n, complex_)
+    Minv = np.linalg.inv(M)
+    AMinv = A @ Minv
+    b, x0 = vec(N, 41, complex_), vec(N, 42, complex_)
+    Q = block(N, n, 43, complex_)
+    pre = (lambda v: np.linalg.solve(M, v), lambda v: np.linalg.solve(M.conj().T, v))
+    K = 3 * n + 6
+    px = mlbicgstabt(A, b, Q, x0=x0, tol=1e-11, maxit=200, kappa=kappa, precond=pre, record_x=K)
+    py = mlbicgstabt(AMinv, b, Q, x0=M @ x0, tol=1e-11, maxit=200, kappa=kappa, record_x=K)
+    assert px.flag == py.flag == 0
+    assert px.iter == py.iter
+    assert len(px.x_history) == len(py.x_history) >= min(K, px.iter)
+    for k, (xk, yk) in enumerate(zip(px.x_history, py.x_history)):
+        ref = Minv @ yk
+        assert np.linalg.norm(xk - ref) <= 1e-10 * np.linalg.norm(ref), k + 1
+    for a, o in zip(px.omegas, py.omegas):
+        assert abs(a - o) <= 1e-10 * abs(o)
+    assert np.linalg.norm(px.x - Minv @ py.x) <= 1e-10 * np.linalg.norm(px.x)
+    assert true_error(A, px.x, b) < 1e-10
 
 
 # --------------------------------------------------------------------------- flags and edge cases

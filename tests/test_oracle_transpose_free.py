@@ -81,9 +81,8 @@ def test_recombined_w_is_A_g(n):
 
     def obs(event, **st):
         if event == "w":
-            i = st["col"]
-            w = st["W"][:, i]
-            worst.append(np.linalg.norm(w - A @ st["G"][:, i]) / np.linalg.norm(w))
+            w = st["w"]
+            worst.append(np.linalg.norm(w - A @ st["g"]) / np.linalg.norm(w))
 
     mlbicgstabt(A, vec(N, 4), block(N, n, 3), tol=1e-300, maxit=4 * n, observer=obs, transpose_free=True)
     assert len(worst) >= 4 * n

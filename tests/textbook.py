@@ -2,6 +2,9 @@
 
 * BiCGStab as van der Vorst published it (SIAM J. Sci. Stat. Comput. 13, 1992),
   with shadow residual r~ = q_1 and the usual early exit on ||s||.
+* The same BiCGStab with the stabilised choice of omega of Sleijpen and
+  van der Vorst (Numer. Algorithms 10, 1995): when the cosine between t = A s
+  and s is below kappa in modulus, omega is enlarged by kappa / |cosine|.
 * BiCG (Fletcher 1976) with shadow residual r~_0 = q_1.
 * FOM and GMRES iterates by brute force: an orthonormal Krylov basis (Arnoldi
   with repeated modified Gram-Schmidt) and a Galerkin solve / least-squares fit.
@@ -41,6 +44,47 @@ def bicgstab(A, b, q, x0=None, tol=1e-10, maxit=100):
             return xs, it, 0
         rho_old = rho
     return xs, maxit, 1
+
+
+def bicgstab_guarded(A, b, q, kappa, tol=1e-10, maxit=100):
+    """BiCGStab with the kappa-guarded omega.  Returns (xs, iters, flag, omegas, fired):
+    omegas[m] is the omega used in iteration m + 1, fired[m] whether the guard changed it."""
+    A = np.asarray(A.toarray() if hasattr(A, "toarray") else A)
+    dt = np.result_type(A.dtype, b.dtype, q.dtype, np.float64)
+    x = np.zeros(len(b), dt)
+    bn = np.linalg.norm(b) or 1.0
+    r = b.astype(dt) - A @ x
+    rt = q.astype(dt)
+    p = r.copy()
+    rho = np.vdot(rt, r)
+    xs, omegas, fired = [], [], []
+    for it in range(1, maxit + 1):
+        v = A @ p
+        alpha = rho / np.vdot(rt, v)
+        s = r - alpha * v
+        if np.linalg.norm(s) / bn < tol:
+            x = x + alpha * p
+            xs.append(x.copy())
+            return xs, it, 0, omegas, fired
+        t = A @ s
+        ts, tt = np.vdot(t, s), np.vdot(t, t).real
+        omega = ts / tt
+        cos = abs(ts) / (np.sqrt(tt) * np.linalg.norm(s))
+        guard = 0 < cos < kappa
+        if guard:
+            omega = omega * (kappa / cos)
+        omegas.append(omega)
+        fired.append(bool(guard))
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        xs.append(x.copy())
+        if np.linalg.norm(r) / bn < tol:
+            return xs, it, 0, omegas, fired
+        rho_new = np.vdot(rt, r)
+        beta = (rho_new / rho) * (alpha / omega)
+        rho = rho_new
+        p = r + beta * (p - omega * v)
+    return xs, maxit, 1, omegas, fired
 
 
 def bicg(A, b, q, steps):
