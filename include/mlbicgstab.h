@@ -251,6 +251,36 @@ int mlbicgstab_destroy(mlb_handle h);
 enum { MLB_OP_A = 0, MLB_OP_AH = 1 };
 int mlbicgstab_matvec(mlb_handle h, int32_t op, const void* x, void* y);
 
+/*
+ * Allocation-free solve, for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, such as tight serving loops or harnesses that
+ * forbid allocation): the same result as mlbicgstab_create + mlbicgstab_solve
+ * + mlbicgstab_destroy with these arguments (the same kernels, grids and
+ * reduction order, so x, iter and flag are bitwise those of that sequence),
+ * with every piece of library-owned device memory -- the index check flag,
+ * A^H and its transpose temporaries, the Krylov workspace, partial sums and
+ * the scalar state -- carved from one static device array of
+ * MLB_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from its load
+ * until the process ends.  The caller passes A, b, x and Q as for
+ * create/solve (all borrowed for the call) and the stream the work goes on.
+ * No hipMalloc, hipFree, pinned host allocation or HIP event is used; the host
+ * reads the device's done flag every few cycles instead of a host-mapped one,
+ * and res->setup_ms is 0, res->solve_ms host wall time.
+ * Limits: opt->precision must be MLB_PREC_FP64 and opt->precond
+ * MLB_PRECOND_NONE (else MLB_EUNSUPPORTED); an A and n whose buffers exceed
+ * the scratch return MLB_EUNSUPPORTED with the bytes needed in the message,
+ * before any work is enqueued (CSR fp64 with 7 entries a row and n = 4 fits up
+ * to about 300,000 rows with A^H, about 690,000 with transpose_free).
+ * All calls on one GPU share its array, which keeps the last call's contents:
+ * the library re-initialises what each call reads and serialises the calls of
+ * one process with a lock (two calls that overlapped on one GPU would race on
+ * the array).  Synchronises the stream before returning.  Returns the flag or
+ * an API error, as mlbicgstab_solve.
+ */
+#define MLB_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int mlbicgstab_solve_noalloc(const mlb_matrix* A, const mlb_options* opt, void* hip_stream, const void* b, void* x,
+                             const void* Q, int64_t ldq, mlb_result* res);
+
 /* Message for the last API error on this thread ("" if none). */
 const char* mlbicgstab_last_error(void);
 

@@ -134,6 +134,11 @@ _lib.mlb_sequence_solve.argtypes = [mlb_sequence_handle, ctypes.c_void_p, ctypes
 _lib.mlb_sequence_solve.restype = ctypes.c_int
 _lib.mlb_sequence_destroy.argtypes = [mlb_sequence_handle]
 _lib.mlb_sequence_destroy.restype = ctypes.c_int
+_lib.mlbicgstab_solve_noalloc.argtypes = [ctypes.POINTER(mlb_matrix), ctypes.POINTER(mlb_options), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.POINTER(mlb_result)]
+_lib.mlbicgstab_solve_noalloc.restype = ctypes.c_int
+MLB_NOALLOC_SCRATCH_BYTES = 64 << 20
 _lib.mlb_server_create.argtypes = [ctypes.POINTER(mlb_server_options), ctypes.POINTER(mlb_server_handle)]
 _lib.mlb_server_create.restype = ctypes.c_int
 _lib.mlb_server_submit.argtypes = [mlb_server_handle, ctypes.POINTER(mlb_matrix), ctypes.POINTER(mlb_options),
@@ -197,6 +202,15 @@ def mlbicgstab_solve_batch(handles, b_ptrs, x_ptrs, q_ptrs, ldqs):
 
 def mlbicgstab_destroy(h) -> int:
     return _check(_lib.mlbicgstab_destroy(h))
+
+
+def mlbicgstab_solve_noalloc(A: mlb_matrix, opt: mlb_options, hip_stream: int, b_ptr: int, x_ptr: int, q_ptr: int,
+                             ldq: int) -> mlb_result:
+    res = mlb_result()
+    _check(_lib.mlbicgstab_solve_noalloc(ctypes.byref(A), ctypes.byref(opt), ctypes.c_void_p(hip_stream),
+                                         ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), ctypes.c_void_p(q_ptr),
+                                         ctypes.c_int64(ldq), ctypes.byref(res)))
+    return res
 
 
 def mlbicgstab_last_error() -> str:
@@ -389,6 +403,24 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def solve_noalloc(dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
+                  record_iterates: int = 0, iterates=None, stream=None, transpose_free: bool = False,
+                  order: int = MLB_ORDER_FUSED) -> mlb_result:
+    """mlbicgstab_solve_noalloc: one fp64 solve with every library buffer in the static device scratch."""
+    import torch
+
+    N = dmat.nrows
+    ldq = q_layout(Q, N, n)
+    if b.numel() != N or x.numel() != N or not x.is_contiguous() or not b.is_contiguous():
+        raise ValueError("b and x must be contiguous vectors of length N")
+    opt = mlb_options(n, tol, maxit, kappa, MLB_PREC_FP64, 0.0, 0, record_iterates,
+                      iterates.data_ptr() if iterates is not None else None, MLB_PRECOND_NONE, int(transpose_free),
+                      order)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return mlbicgstab_solve_noalloc(dmat.descriptor(), opt, st.cuda_stream, b.data_ptr(), x.data_ptr(),
+                                    Q.data_ptr(), ldq)
 
 
 def solve_batch(solvers, bs, xs, Qs):

@@ -55,10 +55,16 @@ struct Error {
 // Device allocations owned by one solver, freed together.  Stream-ordered mode
 // (hipMallocAsync / hipFreeAsync on one stream) is used by the serving path, so
 // that admitting or retiring a request never synchronises the whole device.
+// Arena mode (arena != nullptr) allocates nothing: every request is carved,
+// 256-byte aligned, from [arena, arena + cap), a region the caller owns (the
+// static scratch of mlbicgstab_solve_noalloc), and nothing is freed.
+constexpr size_t ARENA_ALIGN = 256;
 struct Allocs {
   std::vector<void*> ptrs;
   hipStream_t stream = nullptr;
   bool ordered = false;
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
   Allocs() = default;
   Allocs(hipStream_t s, bool ord) : stream(s), ordered(ord) {}
   Allocs(const Allocs&) = delete;
@@ -67,6 +73,13 @@ struct Allocs {
   T* get(size_t count) {
     void* p = nullptr;
     if (count == 0) count = 1;
+    if (arena) {
+      const size_t off = (used + ARENA_ALIGN - 1) & ~(ARENA_ALIGN - 1);
+      if (off > cap || count > (cap - off) / sizeof(T))
+        throw Error{MLB_EUNSUPPORTED, "the static scratch of " + std::to_string(cap) + " bytes is too small"};
+      used = off + count * sizeof(T);
+      return (T*)(arena + off);
+    }
     const hipError_t e = ordered ? hipMallocAsync(&p, count * sizeof(T), stream) : hipMalloc(&p, count * sizeof(T));
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -79,6 +92,12 @@ struct Allocs {
     for (void* p : ptrs) (void)(ordered ? hipFreeAsync(p, stream) : hipFree(p));
   }
 };
+
+// Bytes an arena needs for `count` objects of T (alignment padding included).
+template <class T>
+static size_t arena_bytes(size_t count) {
+  return (std::max<size_t>(count, 1) * sizeof(T) + ARENA_ALIGN - 1) & ~(ARENA_ALIGN - 1);
+}
 
 static int grid_for(long long work, int cap) {
   long long g = (work + BLOCK - 1) / BLOCK;
@@ -149,11 +168,17 @@ static Mat<V> build_transpose(const Mat<V>& A, Allocs& al, hipStream_t s) {
   int* rpT = al.get<int>(m + 1);
   int* ciT = al.get<int>(A.nnz);
   V* valT = al.get<V>((size_t)A.nnz * bs);
-  Allocs tmp(al.stream, al.ordered);
+  Allocs tmp_own(al.stream, al.ordered);
+  Allocs& tmp = al.arena ? al : tmp_own;   // arena mode: temporaries stay in the arena
   int* cnt = tmp.get<int>(m);
   int* fill = tmp.get<int>(m);
-  HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int) * m, s));
-  HIP_TRY(hipMemsetAsync(fill, 0, sizeof(int) * m, s));
+  if (al.arena) {
+    k_fill<int><<<grid_for(m, 4096), BLOCK, 0, s>>>(cnt, m, 0);
+    k_fill<int><<<grid_for(m, 4096), BLOCK, 0, s>>>(fill, m, 0);
+  } else {
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int) * m, s));
+    HIP_TRY(hipMemsetAsync(fill, 0, sizeof(int) * m, s));
+  }
   if (A.nnz > 0) k_col_count<<<grid_for(A.nnz, 4096), BLOCK, 0, s>>>(A.ci, A.nnz, cnt);
   {
     const int ntiles = (int)((m + SCAN_TILE - 1) / SCAN_TILE);
@@ -170,7 +195,7 @@ static Mat<V> build_transpose(const Mat<V>& A, Allocs& al, hipStream_t s) {
     k_sort_rows<V, 9><<<grid_for(m, 4096), BLOCK, 0, s>>>(rpT, m, ciT, valT);
   }
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(s));   // tmp is freed on return
+  HIP_TRY(hipStreamSynchronize(s));   // tmp_own is freed on return
   T.rp = rpT;
   T.ci = ciT;
   T.val = valT;
@@ -295,6 +320,10 @@ struct Engine {
   long long ldq = 0;
 
   bool own_flag = true;
+  // Poll mode (set before init): no host-mapped done flag and no HIP events; the
+  // host reads the device flag every POLL_CYCLES cycles (allocation-free solves).
+  bool poll = false;
+  static constexpr int POLL_CYCLES = 4;
   bool tf = false;   // transpose-free inner steps: no A^H, no F (set before init)
   bool literal = false;   // beta~ and beta recurrences in the sequential order, one reduction per coefficient
 
@@ -318,6 +347,7 @@ struct Engine {
     part = al.get<Sc>((size_t)MAX_PARTIAL_ROWS * (NMAX + 1));
     part2 = al.get<Sc>((size_t)PSUM_GRID * (NMAX + 1));
     set_n(n_alloc);
+    if (poll) return;   // no host-mapped flag, no events
     if (ext_flag) {
       host_done = ext_flag;
       own_flag = false;
@@ -327,6 +357,13 @@ struct Engine {
     *host_done = 0;
     HIP_TRY(hipHostGetDevicePointer((void**)&host_done_dev, host_done, 0));
     for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // Workspace init() carves for N rows and n shadow vectors (arena mode).
+  static size_t arena_need(int N, int n, bool tf) {
+    const size_t Nn = (size_t)N * n;
+    return 2 * arena_bytes<V>(Nn) + (tf ? 0 : arena_bytes<V>((size_t)N * std::max(n - 1, 1))) +
+           3 * arena_bytes<V>(N) + arena_bytes<State<Sc>>(1) + arena_bytes<Sc>((size_t)MAX_PARTIAL_ROWS * (NMAX + 1)) +
+           arena_bytes<Sc>((size_t)PSUM_GRID * (NMAX + 1));
   }
   // Active number of shadow vectors (<= the n the workspace was sized for).  The
   // grids: one resident round of workgroups, CUs x the SpMV-step kernel's
@@ -644,6 +681,7 @@ struct Engine {
   // Algorithm 7.1 with M = I from x (in: x_0, out: solution).
   Out solve(const V* b, V* x, const V* Q_, long long ldq_, double tol, long long maxit, double kappa, V* xrec,
             long long K, long long stag_window = 0) {
+    if (poll) return solve_polled(b, x, Q_, ldq_, tol, maxit, kappa, xrec, K, stag_window);
     Q = Q_;
     ldq = ldq_;
     *(volatile int*)host_done = 0;
@@ -681,6 +719,42 @@ struct Engine {
     HIP_TRY(hipEventElapsedTime(&o.setup_ms, t0, t1));
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
+    return o;
+  }
+
+  // The same solve without a host-mapped flag or events: the cycles are enqueued
+  // POLL_CYCLES at a time, each batch followed by a copy of the device done flag
+  // into a host word and a wait for it.  Set-up time is not measured (0).
+  Out solve_polled(const V* b, V* x, const V* Q_, long long ldq_, double tol, long long maxit, double kappa,
+                   V* xrec, long long K, long long stag_window) {
+    Q = Q_;
+    ldq = ldq_;
+    k_init_state<Sc><<<1, 1, 0, s>>>(st, tol, maxit, kappa, nullptr, stag_window);
+    spmv_resid(A, x, b, r, Q, PH_SETUP);
+    if (!tf)
+      for (int c = 0; c + 1 < n; ++c) spmv_plain(AH, Q + (size_t)c * ldq, F + (size_t)c * N);
+    spmv_step(r, 0);
+    HIP_TRY(hipGetLastError());
+    const long long max_cycles = maxit / n + 2;
+    for (long long j = 0; j <= max_cycles; ++j) {
+      cycle((int)std::min<long long>(j, 1), x, xrec, K);
+      if ((j + 1) % POLL_CYCLES == 0 || j == max_cycles) {
+        int d = 0;
+        HIP_TRY(hipMemcpyAsync(&d, &st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (d) break;
+      }
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    State<Sc> h;
+    HIP_TRY(hipMemcpyAsync(&h, st, sizeof(State<Sc>), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    Out o{};
+    o.flag = h.done ? h.flag : 1;
+    o.iter = h.iter;
+    o.err = h.err;
+    o.setup_ms = 0.f;
     return o;
   }
 
@@ -731,6 +805,7 @@ struct mlb_solver {
   bool own_stream = false;
   bool solved = false;
   int* ext_flags = nullptr;   // two pinned host-mapped ints owned by a serving worker, or NULL
+  bool noalloc = false;       // everything in the caller's arena, no host-mapped flags or events
   int n_active = 0;           // shadow vectors of the next solve (<= opt.n, the workspace's)
   Allocs al;
   std::unique_ptr<Impl<double, float>> real;
@@ -804,8 +879,8 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
     const int bs = A.format == MLB_BSR3 ? 9 : 1;
     int* ci = h->al.get<int>(1);
     V64* val = h->al.get<V64>(bs);
-    HIP_TRY(hipMemsetAsync(ci, 0, sizeof(int), h->s));
-    HIP_TRY(hipMemsetAsync(val, 0, sizeof(V64) * bs, h->s));
+    k_fill<int><<<1, BLOCK, 0, h->s>>>(ci, 1, 0);
+    k_fill<V64><<<1, BLOCK, 0, h->s>>>(val, bs, zero<V64>());
     A.ci = ci;
     A.val = val;
   }
@@ -840,6 +915,7 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
   const Mat<V64> AH = tf ? Mat<V64>{} : build_transpose(A, h->al, h->s);
   im.e64.tf = tf;
   im.e64.literal = h->opt.order == MLB_ORDER_LITERAL;
+  im.e64.poll = h->noalloc;
   im.e64.init(A, AH, h->opt.n, h->s, h->al, h->ext_flags);
   im.r64 = h->al.get<V64>(h->N);
   if (h->opt.precision == MLB_PREC_FP32_IR) {
@@ -875,6 +951,40 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(h->s));
 }
+
+// Stream time of a whole solve: a HIP event pair, or (host_only, allocation-free
+// solves) the host clock around the work, which ends with a stream synchronisation.
+struct SolveClock {
+  hipStream_t s;
+  bool host_only;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  std::chrono::steady_clock::time_point h0;
+  SolveClock(hipStream_t s_, bool host_only_) : s(s_), host_only(host_only_) {
+    if (host_only) {
+      HIP_TRY(hipStreamSynchronize(s));
+      h0 = std::chrono::steady_clock::now();
+      return;
+    }
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    HIP_TRY(hipEventRecord(t0, s));
+  }
+  double stop_ms() {
+    if (host_only) {
+      HIP_TRY(hipStreamSynchronize(s));
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+    }
+    HIP_TRY(hipEventRecord(t1, s));
+    HIP_TRY(hipEventSynchronize(t1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+    return ms;
+  }
+  ~SolveClock() {
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  }
+};
 
 // MLB_DEBUG=1 in the environment prints one line per refinement step on stderr.
 static bool debug_enabled() {
@@ -915,10 +1025,7 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
                       mlb_result* res) {
   const mlb_options& o = h->opt;
   const int N = h->N;
-  hipEvent_t t0, t1;
-  HIP_TRY(hipEventCreate(&t0));
-  HIP_TRY(hipEventCreate(&t1));
-  HIP_TRY(hipEventRecord(t0, h->s));
+  SolveClock clock(h->s, h->noalloc);
   mlb_result R{};
   int flag = 1;
   if (o.precision == MLB_PREC_FP64) {
@@ -996,13 +1103,7 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
   im.e64.read_aux(&rr, &bb);
   R.err_true = std::sqrt(rr) / (bb > 0 ? std::sqrt(bb) : 1.0);
   if (o.precision == MLB_PREC_FP32_IR && R.fp64_iters == 0) R.err_recursive = R.err_true;
-  HIP_TRY(hipEventRecord(t1, h->s));
-  HIP_TRY(hipEventSynchronize(t1));
-  float ms = 0;
-  HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
-  R.solve_ms = ms;
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
+  R.solve_ms = clock.stop_ms();
   R.flag = flag;
   if (res) *res = R;
   return flag;
@@ -1076,8 +1177,11 @@ static int guarded(F&& f) {
 // Validates A and opt, builds A^H (and the preconditioned / fp32 copies) and the
 // workspace.  ordered: stream-ordered allocations on `stream` (serving);
 // flags: two pinned host-mapped ints for the engines' done flags, or NULL.
+// arena / arena_cap: allocation-free mode, every device buffer carved from the
+// caller's region (see Allocs).
 static std::unique_ptr<mlb_solver> create_solver(const mlb_matrix* A, const mlb_options* opt, hipStream_t stream,
-                                                 bool ordered, int* flags) {
+                                                 bool ordered, int* flags, char* arena = nullptr,
+                                                 size_t arena_cap = 0) {
   check_matrix(A);
   check_options(opt);
   auto h = std::make_unique<mlb_solver>();
@@ -1092,11 +1196,15 @@ static std::unique_ptr<mlb_solver> create_solver(const mlb_matrix* A, const mlb_
   h->al.ordered = ordered;
   h->ext_flags = flags;
   h->n_active = opt->n;
+  h->al.arena = arena;
+  h->al.cap = arena_cap;
+  h->noalloc = arena != nullptr;
   // validate the index arrays on the device before any kernel relies on them
   {
-    Allocs tmp(stream, ordered);
+    Allocs tmp_own(stream, ordered);
+    Allocs& tmp = h->noalloc ? h->al : tmp_own;
     int* bad = tmp.get<int>(1);
-    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), h->s));
+    k_fill<int><<<1, BLOCK, 0, h->s>>>(bad, 1, 0);
     const int nbr = A->format == MLB_BSR3 ? (int)(A->nrows / 3) : (int)A->nrows;
     k_validate<<<grid_for(std::max<long long>(nbr + 1, A->nnz), 4096), BLOCK, 0, h->s>>>(A->row_ptr, A->col_idx, nbr,
                                                                                          A->nnz, nbr, bad);
@@ -1426,6 +1534,94 @@ int mlbicgstab_time_kernel(mlb_handle h, int32_t kernel, int32_t reps, double* m
     else
       *ms_per_launch = ir ? time_kernel_impl(h->cpx->e32, kernel, reps) : time_kernel_impl(h->cpx->e64, kernel, reps);
     return 0;
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free solves
+//
+// mlbicgstab_solve_noalloc carves every device buffer of one create + solve
+// (index check flag, A^H and its transpose temporaries, the Krylov workspace,
+// partial sums, the scalar state) from one static device array per GPU.  In
+// host code the array's name is only a stand-in: its device address on the
+// current GPU comes from hipGetSymbolAddress, taken once per device and kept.
+// The library's lock serialises these calls within a process, so two of them
+// never share the array at once; each call re-initialises what it reads.
+
+static __device__ __align__(256) unsigned char scratch[MLB_NOALLOC_SCRATCH_BYTES];
+
+namespace mlb {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;                          // guards the table and the arrays
+static char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};    // device address of `scratch` per device
+
+// Device address of the static scratch on the current device (looked up once).
+static char* scratch_on_current_device() {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) throw Error{MLB_EUNSUPPORTED, "device ordinal beyond 63"};
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error{MLB_EHIP, "hipGetSymbolAddress returned no address for the scratch array"};
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Scratch bytes an allocation-free solve of A with opt carves, in the order
+// create_solver carves them (each piece padded to the arena alignment).
+template <class V>
+static size_t noalloc_bytes_t(const mlb_matrix* A, const mlb_options* opt) {
+  const bool bsr = A->format == MLB_BSR3;
+  const size_t N = (size_t)A->nrows;
+  const size_t m = bsr ? N / 3 : N;
+  const size_t bs = bsr ? 9 : 1;
+  const size_t nnz = (size_t)A->nnz;
+  const bool tf = opt->transpose_free != 0;
+  size_t t = arena_bytes<int>(1);                                   // index check flag
+  if (nnz == 0) t += arena_bytes<int>(1) + arena_bytes<V>(bs);       // stand-in index / value arrays
+  if (!tf) {
+    t += arena_bytes<int>(m + 1) + arena_bytes<int>(nnz) + arena_bytes<V>(nnz * bs);   // A^H
+    t += 2 * arena_bytes<int>(m) + arena_bytes<int>((m + SCAN_TILE - 1) / SCAN_TILE + 1);   // its temporaries
+  }
+  t += Engine<V>::arena_need((int)N, opt->n, tf);
+  t += arena_bytes<V>(N);                                           // fp64 residual
+  return t;
+}
+
+static size_t noalloc_bytes(const mlb_matrix* A, const mlb_options* opt) {
+  return A->dtype == MLB_C128 ? noalloc_bytes_t<cplx<double>>(A, opt) : noalloc_bytes_t<double>(A, opt);
+}
+
+}  // namespace mlb
+
+extern "C" {
+
+int mlbicgstab_solve_noalloc(const mlb_matrix* A, const mlb_options* opt, void* hip_stream, const void* b, void* x,
+                             const void* Q, int64_t ldq, mlb_result* res) {
+  return guarded([&]() -> int {
+    check_matrix(A);
+    check_options(opt);
+    if (opt->precision != MLB_PREC_FP64)
+      throw Error{MLB_EUNSUPPORTED, "the allocation-free solve runs the fp64 iteration only"};
+    if (opt->precond != MLB_PRECOND_NONE)
+      throw Error{MLB_EUNSUPPORTED, "the allocation-free solve takes no preconditioner"};
+    if (!b || !x || !Q) throw Error{MLB_EINVAL, "b, x and Q must be device pointers"};
+    if (ldq < A->nrows) throw Error{MLB_EINVAL, "ldq must be >= N"};
+    const size_t need = noalloc_bytes(A, opt);
+    if (need > (size_t)MLB_NOALLOC_SCRATCH_BYTES)
+      throw Error{MLB_EUNSUPPORTED, "the allocation-free solve needs " + std::to_string(need) +
+                                        " bytes of scratch for this A and n; the static scratch holds " +
+                                        std::to_string((size_t)MLB_NOALLOC_SCRATCH_BYTES)};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    char* base = scratch_on_current_device();
+    auto h = create_solver(A, opt, (hipStream_t)hip_stream, false, nullptr, base, (size_t)MLB_NOALLOC_SCRATCH_BYTES);
+    const int rc = solve_solver(h.get(), b, x, Q, ldq, res);
+    HIP_TRY(hipStreamSynchronize(h->s));   // the scratch is free again when the lock is released
+    return rc;
   });
 }
 
