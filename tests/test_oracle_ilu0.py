@@ -221,8 +221,7 @@ def _pins_hold(mod):
 
 
 def test_unmutated_ilu0_passes():
-    import oracle.ilu0 as m
-    assert _pins_hold(m)
+    assert _pins_hold(sys.modules["oracle.ilu0"])   # the module (the package re-exports a function of that name)
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
