@@ -7,6 +7,11 @@ x_0 = 0, tol 1e-10.  Default workload: the 3D convection-diffusion system on a
 workloads (--workload reservoir: 60x220x85 3x3-block system, BSR3, n = 8;
 --workload helmholtz: complex 96^3 system, n = 16) and the fp32-inner /
 fp64-refinement mode (--precision ir) use the same step definition.
+
+The default line also carries, under "secondary", one record per other
+configuration (the reservoir system in fp64 and fp32-IR, the complex system
+with n = 16, and the 2000-request serving trace in fp32-IR beside the same
+requests solved one after another in fp64); --no-extras leaves them out.
 Prints one JSON line.  Progress goes to stderr.
 """
 import argparse
@@ -41,6 +46,36 @@ def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False, literal=False):
     mat = nnz * ((9 if bsr else 1) * sv + 4) + 4 * (nbrows + 1)
     vec_avg = 3.0 if literal else sum(1 + (n - i) + 1 for i in range(n)) / n
     return mat + vec_avg * N * sv
+
+
+def matrix_bytes(nnz, nbrows, sv, bsr=False):
+    """Compulsory bytes of one pass over A: values, column indices, row pointers."""
+    return nnz * ((9 if bsr else 1) * sv + 4) + 4 * (nbrows + 1)
+
+
+def vector_passes_per_iter(n, transpose_free=False):
+    """Vectors of N values the kernels of one iteration read or write, averaged over a cycle of n steps
+    (the SpMV's gathered input and output included; each vector counted once per pass).
+
+    Per inner step i = 1..n-1: alpha pass 6 + n - i, combination 2 + 2(n - i) + i, recombination
+    2 + i, SpMV step 2 + (n - i); per cycle end: half step 6, SpMV of the minimisation step 2, omega
+    pass 5 + n, cycle close 2 + 2n, SpMV step 2 + n.  Transpose-free steps replace the recombination and
+    the product of g_k by the product of g (2 + i, its shadow dots) and the recombination of g and w
+    (4 + 2i + n - i), and read no F (combination 2 + 2(n - i))."""
+    total = 0
+    for i in range(1, n):
+        if transpose_free:
+            total += (6 + n - i) + (2 + 2 * (n - i)) + (2 + i) + (4 + 2 * i + n - i)
+        else:
+            total += (6 + n - i) + (2 + 2 * (n - i) + i) + (2 + i) + (2 + n - i)
+    total += 6 + 2 + (5 + n) + (2 + 2 * n) + (2 + n)
+    return total / n
+
+
+def bytes_per_iter(nnz, nbrows, N, n, sv, bsr=False, transpose_free=False):
+    """Algorithmic bytes of one iteration of the kernels as built: (1 + 1/n) passes over A plus the
+    vector passes above."""
+    return (1 + 1 / n) * matrix_bytes(nnz, nbrows, sv, bsr) + vector_passes_per_iter(n, transpose_free) * N * sv
 
 
 def copy_rate_gbs(torch, dev, gib=1.0, reps=5):
@@ -83,32 +118,92 @@ def measured_traffic(workload, root=ROOT):
     return int(m_t.group(1))
 
 
-def cpu_baseline(p, iters_gpu, sample_iters, target_s=15.0):
-    """The oracle on this host, on one core: a bounded sample of the same solve, scaled to the
-    GPU's iteration count.  A 5-iteration probe sets the sample length to about target_s of CPU
-    time (at most the GPU's iteration count, and at most sample_iters when that is > 0)."""
+def host_info():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "affinity": aff}
+
+
+def host_threads():
+    """Threads for the all-core oracle run: OMP_NUM_THREADS when set (the machine's CPU share), else the
+    CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return int(env) if env.isdigit() and int(env) > 0 else host_info()["affinity"]
+
+
+def host_add_gbs(threads, mib=512, reps=3):
+    """Host memory bandwidth, STREAM-add style: a = b + c over `threads` contiguous slices in parallel
+    (numpy releases the GIL), 3 arrays of `mib` MiB moved per pass; the best of `reps` passes, GB/s."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    n = mib * (1 << 20) // 8
+    a, b, c = np.empty(n), np.ones(n), np.ones(n)
+    bounds = np.linspace(0, n, threads + 1).astype(int)
+    sl = [slice(bounds[i], bounds[i + 1]) for i in range(threads)]
+    best = float("inf")
+    with ThreadPoolExecutor(threads) as ex:
+        for _ in range(reps + 1):
+            t0 = time.perf_counter()
+            list(ex.map(lambda q: np.add(b[q], c[q], out=a[q]), sl))
+            best = min(best, time.perf_counter() - t0)
+    return 3 * n * 8 / best / 1e9
+
+
+def cpu_baseline(p, iters_gpu, sample_iters, bytes_per_iter, target_s=10.0, add_mib=512):
+    """The oracle on this host: a bounded sample of the same solve, on one core and on all the cores
+    this process has (BLAS threads; scipy's sparse products stay on one thread).
+
+    A 5-iteration probe sizes the sample to about target_s of single-core time: the whole solve (the
+    oracle then runs to its own convergence, and the sample counts as whole only if it converged)
+    when that fits in twice target_s, else that many iterations, scaled to the GPU's iteration count.
+    `value` is the all-core time; the single-core run is reported beside it, with the host's CPU model
+    and an add-kernel bandwidth figure for the bandwidth fraction of the all-core run."""
     from threadpoolctl import threadpool_limits
 
     import oracle
 
-    def run(maxit):
-        t0 = time.perf_counter()
-        o = oracle.mlbicgstabt(p.A, p.b, p.Q, x0=p.x0, tol=p.tol, maxit=maxit, kappa=p.kappa)
-        return o, time.perf_counter() - t0
+    def run(maxit, threads):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            o = oracle.mlbicgstabt(p.A, p.b, p.Q, x0=p.x0, tol=p.tol, maxit=maxit, kappa=p.kappa)
+            return o, time.perf_counter() - t0
 
-    with threadpool_limits(limits=1):
-        o, dt = run(5)
-        n_it = max(5, min(iters_gpu, int(target_s * o.iter / max(dt, 1e-9))))
-        if sample_iters > 0:
-            n_it = min(n_it, sample_iters)
-        if n_it > o.iter and o.flag == 1:
-            o, dt = run(n_it)
+    threads = host_threads()
+    o, dt = run(5, 1)
     per_it = dt / max(o.iter, 1)
-    whole = o.iter >= iters_gpu
-    return {"value": dt if whole else per_it * iters_gpu, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"the whole solve ({o.iter} iterations, setup included) on 1 core" if whole else
-                       f"first {o.iter} iterations of the same solve (setup included) took {dt:.2f} s on 1 core; "
-                       f"scaled to the GPU's {iters_gpu} iterations")}
+    whole_fits = per_it * iters_gpu <= 2 * target_s and sample_iters <= 0
+    maxit = p.maxit if whole_fits else max(5, min(iters_gpu, int(target_s / per_it),
+                                                  sample_iters if sample_iters > 0 else iters_gpu))
+    out = {}
+    for label, th in (("single", 1), ("all", threads)):
+        o, dt = run(maxit, th)
+        whole = o.flag == 0
+        out[label] = {"seconds": dt if whole else dt / max(o.iter, 1) * iters_gpu, "oracle_flag": int(o.flag),
+                      "oracle_iter": int(o.iter), "measured_s": dt, "whole": whole, "threads": th}
+    host = host_info()
+    add_gbs = host_add_gbs(threads, mib=add_mib)
+    a = out["all"]
+    bw = bytes_per_iter * a["oracle_iter"] / a["measured_s"] / 1e9
+    sample = (f"the whole solve on {threads} threads: the oracle converged (flag 0) at {a['oracle_iter']} "
+              f"iterations, setup included" if a["whole"] else
+              f"first {a['oracle_iter']} iterations of the same solve on {threads} threads (oracle flag "
+              f"{a['oracle_flag']}: not converged) took {a['measured_s']:.2f} s, scaled to the GPU's {iters_gpu} "
+              f"iterations")
+    return {"value": a["seconds"], "unit": "s", "cores": threads, "kind": "oracle", "sample": sample,
+            "oracle_flag": a["oracle_flag"], "oracle_iter": a["oracle_iter"], "whole": a["whole"],
+            "single_core": {"value": out["single"]["seconds"], "oracle_flag": out["single"]["oracle_flag"],
+                            "oracle_iter": out["single"]["oracle_iter"], "whole": out["single"]["whole"]},
+            "host": {**host, "add_bandwidth_gbs": add_gbs, "threads_used": threads},
+            "algorithmic_gbs": bw, "bandwidth_frac": bw / add_gbs}
 
 
 def bench_serving(args, torch, workloads, binding):
@@ -282,8 +377,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM admission budget")
     ap.add_argument("--small-n-max", type=int, default=0,
                     help="serving: largest N batched in one-workgroup launches (0 = library default, -1 = none)")
-    ap.add_argument("--serve-precision", default="fp64", choices=["fp64", "ir"],
-                    help="serving: iteration precision (fp32-IR doubles the iteration count on these systems)")
+    ap.add_argument("--serve-precision", default="ir", choices=["fp64", "ir"],
+                    help="serving: iteration precision (the serving configuration names fp32-IR)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "ir"])
     ap.add_argument("--n", type=int, default=0, help="number of shadow vectors (0 = the workload's)")
     ap.add_argument("--m", type=int, default=0, help="grid points per dimension (0 = the workload's)")
@@ -297,6 +392,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="cap on the oracle sample (iterations); 0: about 15 s of CPU time")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary workloads (reservoir fp64 / fp32-IR, complex n = 16, serving)")
+    ap.add_argument("--extra-steps", type=int, default=2, help="timed solves per secondary workload")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB 3 times (counter calibration)")
@@ -321,15 +419,7 @@ def main():
         print(json.dumps(bench_sequence(args, torch, workloads, binding)), flush=True)
         return
     t = time.perf_counter()
-    if args.workload == "convdiff3d":
-        p = workloads.config2(n=args.n or 4, m=args.m or 128)
-        fmt, cplx, grid = "csr", False, [args.m or 128] * 3
-    elif args.workload == "reservoir":
-        p = workloads.config3(n=args.n or 8)
-        fmt, cplx, grid = "bsr3", False, list(p.meta["grid"])
-    else:
-        p = workloads.config5(n=args.n or 16, m=args.m or 96)
-        fmt, cplx, grid = "csr", True, [args.m or 96] * 3
+    p, fmt, cplx, grid = make_problem(args.workload, workloads, args.n, args.m)
     nnz = int(p.A.indptr[-1])          # entries (CSR) or 3x3 blocks (BSR3)
     profile_key = {"convdiff3d": f"convdiff3d_m{args.m or 128}_n{p.n}", "reservoir": f"reservoir_n{p.n}",
                    "helmholtz": f"helmholtz_m{args.m or 96}_n{p.n}"}[args.workload]
@@ -341,41 +431,11 @@ def main():
         profile_key += "_literal"
     nbrows = len(p.A.indptr) - 1
     log(f"[bench] generated {p.name}: N={p.N} stored={nnz} in {time.perf_counter() - t:.1f} s")
-    dA = binding.to_device(p.A, dev)
-    tdt = torch.complex128 if cplx else torch.float64
-    b = torch.from_numpy(p.b.astype(np.complex128 if cplx else np.float64)).to(dev)
-    Q = binding.column_major(p.Q, dev)
-    x = torch.zeros(p.N, dtype=tdt, device=dev)
-    prec = binding.MLB_PREC_FP32_IR if args.precision == "ir" else binding.MLB_PREC_FP64
     use_jacobi = args.precond == "jacobi" or (args.precond == "auto" and args.workload == "reservoir")
-    torch.cuda.synchronize()
-    t_create = time.perf_counter()
-    solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=args.inner_tol,
-                            precond=binding.MLB_PRECOND_JACOBI if use_jacobi else binding.MLB_PRECOND_NONE,
-                            transpose_free=args.transpose_free,
-                            order=binding.MLB_ORDER_LITERAL if args.order == "literal" else binding.MLB_ORDER_FUSED)
-    torch.cuda.synchronize()
-    create_ms = 1e3 * (time.perf_counter() - t_create)   # validation, A^H (and M^{-1} / fp32 copies)
-
-    def step():
-        x.zero_()
-        return solver.solve(b, x, Q)
-
-    for w in range(args.warmup):
-        r = step()
-        log(f"[bench] warmup {w}: flag={r.flag} iter={r.iter} err_true={r.err_true:.3e} solve_ms={r.solve_ms:.1f}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for k in range(args.steps):
-        results.append(step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for k, r in enumerate(results):
-        log(f"[bench] step {k}: flag={r.flag} iter={r.iter} outer={r.outer_iters} fp64_iters={r.fp64_iters} "
-            f"err_rec={r.err_recursive:.3e} err_true={r.err_true:.3e} solve_ms={r.solve_ms:.1f} setup_ms={r.setup_ms:.2f}")
-    ms = 1e3 * elapsed / args.steps
-    last = results[-1]
+    run = timed_solves(torch, binding, p, dev, args.precision, use_jacobi, args.transpose_free, args.order,
+                       args.steps, args.warmup, args.inner_tol, keep_solver=True)
+    solver = run.pop("solver")
+    ms, last = run["ms"], run["last"]
 
     # Dominant kernel (SpMV with its fused combination and shadow dots), timed live with HIP
     # events on the solver's stream, over the workspace of the last solve.
@@ -402,6 +462,10 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {nel * 8} bytes read and written per launch, 3 launches")
         del src, dst
+    # whole solve against the roofline: the kernels' algorithmic bytes over all iterations (fp64 iteration)
+    bpi = bytes_per_iter(nnz, nbrows, p.N, p.n, 16 if cplx else 8, bsr=(fmt == "bsr3"),
+                         transpose_free=args.transpose_free)
+    whole_gbs = bpi * int(last.iter) / (ms * 1e-3) / 1e9 if args.precision == "fp64" else None
 
     line = {
         "metric": "time-to-1e-10 residual",
@@ -436,7 +500,7 @@ def main():
             "err_true": last.err_true,
             "err_recursive": last.err_recursive,
             "setup_ms": last.setup_ms,
-            "matrix_setup_ms": create_ms,
+            "matrix_setup_ms": run["create_ms"],
         },
         "roofline": {
             "kernel": "k_spmv_csrw / k_spmv_bsrw / k_spmv (SpMV step: w_i = A g_i with q_s^H w_i, s >= i)",
@@ -450,12 +514,120 @@ def main():
             "us_per_launch": ms_spmv * 1e3,
             "copy_ceiling": copy_gbs,
             "frac_of_copy": achieved / copy_gbs,
+            "whole_solve_bytes_per_iter": bpi,
+            "whole_solve_gbs": whole_gbs,
+            "whole_solve_frac": whole_gbs / PEAK_HBM_GBS if whole_gbs else None,
+            "other_kernels_us": {"alpha": ms_alpha * 1e3, "combine": ms_comb * 1e3, "recombine": ms_recomb * 1e3},
         },
     }
     if not args.no_cpu:
         log("[bench] timing the oracle sample on the host")
-        line["cpu_baseline"] = cpu_baseline(p, int(last.iter), args.cpu_iters)
+        line["cpu_baseline"] = cpu_baseline(p, int(last.iter), args.cpu_iters, bpi)
+        log(f"[bench] oracle: {line['cpu_baseline']['sample']}")
+    del dA_keep[:]
+    if not args.no_extras and args.workload == "convdiff3d" and args.steps > 0:
+        line["secondary"] = secondary_workloads(args, torch, workloads, binding, dev)
     print(json.dumps(line), flush=True)
+
+
+def make_problem(workload, workloads, n=0, m=0):
+    """(problem, storage, complex?, grid) of a solve workload."""
+    if workload == "convdiff3d":
+        return workloads.config2(n=n or 4, m=m or 128), "csr", False, [m or 128] * 3
+    if workload == "reservoir":
+        p = workloads.config3(n=n or 8)
+        return p, "bsr3", False, list(p.meta["grid"])
+    return workloads.config5(n=n or 16, m=m or 96), "csr", True, [m or 96] * 3
+
+
+dA_keep = []
+
+
+def timed_solves(torch, binding, p, dev, precision, jacobi, transpose_free, order, steps, warmup, inner_tol=0.0,
+                 keep_solver=False):
+    """Upload p, create a solver, run `warmup` untimed and `steps` timed solves from x_0 = 0 (bracketed by
+    device synchronisations); returns ms per solve, the last result and the solver set-up time."""
+    cplx = np.iscomplexobj(p.A.data)
+    dA = binding.to_device(p.A, dev)
+    dA_keep.append(dA)
+    tdt = torch.complex128 if cplx else torch.float64
+    b = torch.from_numpy(p.b.astype(np.complex128 if cplx else np.float64)).to(dev)
+    Q = binding.column_major(p.Q, dev)
+    x = torch.zeros(p.N, dtype=tdt, device=dev)
+    prec = binding.MLB_PREC_FP32_IR if precision == "ir" else binding.MLB_PREC_FP64
+    torch.cuda.synchronize()
+    t_create = time.perf_counter()
+    solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=inner_tol,
+                            precond=binding.MLB_PRECOND_JACOBI if jacobi else binding.MLB_PRECOND_NONE,
+                            transpose_free=transpose_free,
+                            order=binding.MLB_ORDER_LITERAL if order == "literal" else binding.MLB_ORDER_FUSED)
+    torch.cuda.synchronize()
+    create_ms = 1e3 * (time.perf_counter() - t_create)   # validation, A^H (and M^{-1} / fp32 copies)
+
+    def step():
+        x.zero_()
+        return solver.solve(b, x, Q)
+
+    for w in range(warmup):
+        r = step()
+        log(f"[bench] {p.name} {precision} warmup {w}: flag={r.flag} iter={r.iter} err_true={r.err_true:.3e} "
+            f"solve_ms={r.solve_ms:.1f}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for k, r in enumerate(results):
+        log(f"[bench] {p.name} {precision} step {k}: flag={r.flag} iter={r.iter} outer={r.outer_iters} "
+            f"fp64_iters={r.fp64_iters} err_rec={r.err_recursive:.3e} err_true={r.err_true:.3e} "
+            f"solve_ms={r.solve_ms:.1f} setup_ms={r.setup_ms:.2f}")
+    out = {"ms": 1e3 * elapsed / max(steps, 1), "last": results[-1] if results else None, "create_ms": create_ms}
+    if keep_solver:
+        out["solver"] = solver
+    else:
+        solver.close()
+    return out
+
+
+def secondary_workloads(args, torch, workloads, binding, dev):
+    """The other configurations of the benchmark, one line each, so that every headline claim has a
+    measured record: the reservoir system in fp64 and in fp32-IR, the complex Helmholtz system with
+    n = 16, and the serving trace in fp32-IR beside the same requests as sequential fp64 solves."""
+    out = {}
+    for name, wl, precs in (("reservoir_n8", "reservoir", ("fp64", "ir")), ("helmholtz_m96_n16", "helmholtz", ("fp64",))):
+        t = time.perf_counter()
+        p, fmt, cplx, grid = make_problem(wl, workloads)
+        log(f"[bench] secondary: generated {p.name} in {time.perf_counter() - t:.1f} s")
+        nnz, nbrows = int(p.A.indptr[-1]), len(p.A.indptr) - 1
+        bpi = bytes_per_iter(nnz, nbrows, p.N, p.n, 16 if cplx else 8, bsr=(fmt == "bsr3"))
+        rec = {"N": p.N, "n": p.n, "format": fmt, "preconditioner": "block Jacobi (right)" if wl == "reservoir" else
+               "none", "steps": args.extra_steps, "warmup": 1}
+        for prec in precs:
+            r = timed_solves(torch, binding, p, dev, prec, wl == "reservoir", False, "fused", args.extra_steps, 1)
+            last = r["last"]
+            e = {"ms_per_solve": r["ms"], "iterations": int(last.iter), "flag": int(last.flag),
+                 "err_true": last.err_true, "outer_iters": int(last.outer_iters), "fp64_iters": int(last.fp64_iters)}
+            if prec == "fp64":
+                e["whole_solve_gbs"] = bpi * int(last.iter) / (r["ms"] * 1e-3) / 1e9
+                e["whole_solve_frac"] = e["whole_solve_gbs"] / PEAK_HBM_GBS
+                e["ms_per_iter"] = r["ms"] / max(int(last.iter), 1)
+            rec[prec] = e
+            dA_keep.clear()
+            torch.cuda.empty_cache()
+        if "ir" in rec:
+            rec["ir_vs_fp64_time"] = rec["ir"]["ms_per_solve"] / rec["fp64"]["ms_per_solve"]
+        out[name] = rec
+    sargs = argparse.Namespace(**vars(args))
+    sargs.serve_precision = "ir"
+    sargs.transpose_free = False
+    sv = bench_serving(sargs, torch, workloads, binding)
+    out["serving_ir"] = {"solves_per_s": sv["value"], "latency_ms": sv["latency_ms"], "config": sv["config"],
+                         "saturated_solves_per_s": sv["saturated"]["solves_per_s"],
+                         "sequential_fp64_solves_per_s": sv["sequential_fp64"]["solves_per_s"],
+                         "sequential_fp64_max_err_true": sv["sequential_fp64"]["max_err_true"],
+                         "speedup_saturated_vs_sequential_fp64": sv["saturated"]["solves_per_s"] /
+                         sv["sequential_fp64"]["solves_per_s"]}
+    return out
 
 
 if __name__ == "__main__":

@@ -81,12 +81,15 @@ def oracle_spread(p, base, K=20, precond=0, transpose_free=False, n_perturb=1):
     Re-runs the oracle (a) with its inner products summed in other orders
     (correctly rounded, reversed) and (b) with b scaled entrywise by
     (1 + 1e-15 xi), xi ~ N(0, 1), n_perturb times (the k-th perturbed run sums
-    in the k-th of the orders blas, exact, reversed).  Returns (max relative
-    iterate change over k <= K, max |iteration count change|, max true residual,
-    max relative change of the final x).  Two correct fp64 implementations that
+    in the k-th of the orders blas, exact, reversed).  Returns a dict: the max
+    relative iterate change over k <= K ("iterates"), the max |iteration count
+    change| ("iterations") and the range of counts over all runs, base included
+    ("iter_min", "iter_max"), the largest true residual ("true_max") and the max
+    relative change of the final x ("x").  Two correct fp64 implementations that
     only differ in rounding order cannot be expected to agree better than this.
     """
     it_spread, n_spread, true_max, x_spread = 0.0, 0, oracle.true_error(p.A, base.x, p.b), 0.0
+    lo = hi = base.iter
     g = np.random.default_rng(1)
     variants = [("exact", p.b), ("reversed", p.b)]
     for k in range(n_perturb):
@@ -99,6 +102,62 @@ def oracle_spread(p, base, K=20, precond=0, transpose_free=False, n_perturb=1):
         for k in range(kk):
             it_spread = max(it_spread, rel(o2.x_history[k], base.x_history[k]))
         n_spread = max(n_spread, abs(o2.iter - base.iter))
+        lo, hi = min(lo, o2.iter), max(hi, o2.iter)
         true_max = max(true_max, oracle.true_error(p.A, o2.x, p.b))
         x_spread = max(x_spread, rel(o2.x, base.x))
-    return it_spread, n_spread, true_max, x_spread
+    return {"iterates": it_spread, "iterations": n_spread, "iter_min": lo, "iter_max": hi, "true_max": true_max,
+            "x": x_spread}
+
+
+# Caps on the bars widened to the oracle's rounding spread: whatever the spread, a GPU result keeps its
+# first iterates within 1e-6 and its final x within 1e-6 of the oracle's, and its iteration count within
+# 15% of the oracle's (mode "sensitive") or of the range the oracle's own perturbed runs took (mode
+# "chaotic", for the systems whose count moves by more than 15% under rounding alone).
+CAP_ITERATES, CAP_ITERATIONS, CAP_X = 1e-6, 0.15, 1e-6
+
+
+def parity_bars(p, o, K=20, mode="strict", precond=0, transpose_free=False, n_perturb=24, x_tol=1e-6):
+    """The bars one GPU result is held to against the oracle result o.
+
+    strict   : x_1..x_K within 1e-8, iterations within 5% (at least 1), true residual below tol + 1e-12,
+               final x within x_tol.
+    sensitive: each bar widened to the oracle's spread under rounding (10x the iterate and x spread,
+               2x the count spread, the oracle's own largest true residual), then capped as above.
+    chaotic  : as sensitive, but the iteration count must lie in [0.85 min, 1.15 max] of the counts the
+               oracle's own runs took.
+    Returns a dict with iterate bar "it", count range "n_lo".."n_hi", residual bar "res", x bar "x"."""
+    n_tol = max(1, int(0.05 * o.iter))
+    b = {"it": 1e-8, "n_lo": o.iter - n_tol, "n_hi": o.iter + n_tol, "res": p.tol + 1e-12, "x": x_tol}
+    if mode == "strict":
+        return b
+    s = oracle_spread(p, o, K, precond=precond, transpose_free=transpose_free, n_perturb=n_perturb)
+    print(f"  oracle spread: iterates {s['iterates']:.2e} iterations {s['iterations']} "
+          f"(range {s['iter_min']}..{s['iter_max']}) true residual {s['true_max']:.2e} x {s['x']:.2e}")
+    b["it"] = min(max(b["it"], 10 * s["iterates"]), CAP_ITERATES)
+    b["res"] = max(b["res"], s["true_max"])
+    b["x"] = min(max(b["x"], 10 * s["x"]), CAP_X)
+    if mode == "sensitive":
+        n_tol = min(max(n_tol, 2 * s["iterations"]), max(1, int(CAP_ITERATIONS * o.iter)))
+        b["n_lo"], b["n_hi"] = o.iter - n_tol, o.iter + n_tol
+    else:
+        b["n_lo"], b["n_hi"] = int((1 - CAP_ITERATIONS) * s["iter_min"]), int((1 + CAP_ITERATIONS) * s["iter_max"]) + 1
+    return b
+
+
+def check_against_bars(tag, p, res, x, its, o, b, K=20):
+    """Asserts one GPU result against the bars of parity_bars, printing each achieved value beside its bar."""
+    kk = min(K, o.iter, res.iter)
+    worst_it = max((rel(its[k], o.x_history[k]) for k in range(kk)), default=0.0)
+    x_rel = rel(x, o.x)
+    print(f"{p.name}{tag}: N={p.N} n={p.n} gpu flag={res.flag} iter={res.iter} err={res.err_recursive:.3e} "
+          f"true={res.err_true:.3e} | oracle flag={o.flag} iter={o.iter} err={o.err:.3e}", flush=True)
+    print(f"  achieved / bar: iterates {worst_it:.2e} / {b['it']:.0e}, iterations {res.iter} in "
+          f"[{b['n_lo']}, {b['n_hi']}], true residual {res.err_true:.2e} / {b['res']:.2e}, "
+          f"x {x_rel:.2e} / {b['x']:.0e}", flush=True)
+    assert res.flag == o.flag
+    assert b["n_lo"] <= res.iter <= b["n_hi"], (res.iter, o.iter, b["n_lo"], b["n_hi"])
+    for k in range(kk):
+        assert rel(its[k], o.x_history[k]) < b["it"], (k + 1, rel(its[k], o.x_history[k]), b["it"])
+    if o.flag == 0:
+        assert res.err_true < b["res"], (res.err_true, b["res"])
+        assert x_rel < b["x"], (x_rel, b["x"])

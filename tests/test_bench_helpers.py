@@ -49,18 +49,32 @@ def test_committed_profiles_parse():
 
 
 def test_cpu_baseline_sample_is_bounded():
-    """The oracle baseline runs a bounded sample: the whole solve when it is short, else about
-    target_s of CPU time scaled to the GPU's iteration count, and never beyond an explicit cap."""
+    """The oracle baseline runs a bounded sample: the whole solve when it is short (counted as whole only
+    when the oracle converged), else about target_s of CPU time scaled to the GPU's iteration count, and
+    never beyond an explicit cap; both the single-core and the all-core runs are reported."""
     import workloads
 
     p = workloads.config1(n=4)
-    whole = bench.cpu_baseline(p, 69, 0, target_s=30.0)
-    assert whole["cores"] == 1 and whole["kind"] == "oracle" and "whole solve" in whole["sample"]
-    capped = bench.cpu_baseline(p, 69, 10, target_s=30.0)
-    assert "first 10 iterations" in capped["sample"]
+    whole = bench.cpu_baseline(p, 69, 0, 1e6, target_s=30.0, add_mib=8)
+    assert whole["kind"] == "oracle" and "whole solve" in whole["sample"] and whole["whole"]
+    assert whole["oracle_flag"] == 0 and whole["oracle_iter"] == 69
+    assert whole["single_core"]["whole"] and whole["single_core"]["oracle_iter"] == 69
+    assert whole["cores"] >= 1 and whole["host"]["threads_used"] == whole["cores"]
+    assert whole["host"]["add_bandwidth_gbs"] > 0 and 0 < whole["bandwidth_frac"]
+    capped = bench.cpu_baseline(p, 69, 10, 1e6, target_s=30.0, add_mib=8)
+    assert "first 10 iterations" in capped["sample"] and not capped["whole"] and capped["oracle_flag"] == 1
     assert capped["value"] > 0
-    short = bench.cpu_baseline(p, 69, 0, target_s=1e-6)
+    short = bench.cpu_baseline(p, 69, 0, 1e6, target_s=1e-6, add_mib=8)
     assert "first 5 iterations" in short["sample"]
+
+
+def test_vector_passes_by_hand():
+    """n = 2: inner step i = 1 moves (6 + 1) + (2 + 2 + 1) + (2 + 1) + (2 + 1) = 18 vectors, the cycle end
+    6 + 2 + 7 + 6 + 4 = 25; 43 per cycle of 2 iterations.  n = 1 (BiCGStab): 21 per iteration."""
+    assert bench.vector_passes_per_iter(2) == 43 / 2
+    assert bench.vector_passes_per_iter(1) == 21
+    # transpose-free, n = 2: (6 + 1) + (2 + 2) + (2 + 1) + (4 + 2 + 1) = 21 per inner step
+    assert bench.vector_passes_per_iter(2, transpose_free=True) == (21 + 25) / 2
 
 
 def test_spmv_step_bytes_literal_order():

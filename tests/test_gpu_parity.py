@@ -9,7 +9,7 @@ import pytest
 import scipy.sparse as sp
 
 import workloads
-from tests.gpu_util import gpu_available, oracle_spread, rel, run_gpu, run_oracle
+from tests.gpu_util import check_against_bars, gpu_available, parity_bars, rel, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -19,30 +19,14 @@ if not gpu_available():
 from paper_1106_3678_amd import binding  # noqa: E402
 
 
-def check_parity(p, K=20, x_tol=1e-6, sensitive=False, precond=0, n_perturb=1):
-    """Strict bars; with sensitive=True each bar is widened to what the oracle's own
-    rounding-level spread (tests.gpu_util.oracle_spread) allows.  precond=1 compares
-    Algorithm 7.1 with M = the block diagonal of A on both sides."""
+def check_parity(p, K=20, x_tol=1e-6, mode="strict", precond=0, n_perturb=24):
+    """The GPU solve against the oracle under the bars of tests.gpu_util.parity_bars (strict, or widened
+    to the oracle's own rounding spread and capped).  precond=1 compares Algorithm 7.1 with M = the block
+    diagonal of A on both sides."""
     res, x, its = run_gpu(p, record=K, precond=precond)
     o = run_oracle(p, record=K, precond=precond)
-    it_tol, n_tol, res_tol = 1e-8, max(1, int(0.05 * o.iter)), p.tol + 1e-12
-    if sensitive:
-        s_it, s_n, s_true, s_x = oracle_spread(p, o, K, precond=precond, n_perturb=n_perturb)
-        it_tol = max(it_tol, 10 * s_it)
-        n_tol = max(n_tol, 2 * s_n)
-        res_tol = max(res_tol, 3 * s_true)
-        x_tol = max(x_tol, 10 * s_x)
-        print(f"  oracle spread: iterates {s_it:.2e} iterations {s_n} true residual {s_true:.2e} x {s_x:.2e}")
-    print(f"{p.name}: N={p.N} n={p.n} gpu flag={res.flag} iter={res.iter} err={res.err_recursive:.3e} "
-          f"true={res.err_true:.3e} | oracle flag={o.flag} iter={o.iter} err={o.err:.3e}", flush=True)
-    assert res.flag == o.flag
-    assert abs(res.iter - o.iter) <= n_tol, (res.iter, o.iter, n_tol)
-    kk = min(K, o.iter, res.iter)
-    for k in range(kk):
-        assert rel(its[k], o.x_history[k]) < it_tol, (k + 1, rel(its[k], o.x_history[k]), it_tol)
-    if o.flag == 0:
-        assert res.err_true < res_tol, (res.err_true, res_tol)
-        assert rel(x, o.x) < x_tol, (rel(x, o.x), x_tol)
+    b = parity_bars(p, o, K, mode, precond=precond, n_perturb=n_perturb, x_tol=x_tol)
+    check_against_bars("", p, res, x, its, o, b, K)
     return res, o
 
 
@@ -172,22 +156,40 @@ def test_convdiff3d_48():
     check_parity(workloads.config2(n=4, m=48, maxit=4000))
 
 
-@pytest.mark.parametrize("grid,n", [((8, 10, 6), 4), ((12, 16, 6), 8), ((9, 14, 7), 4)])
-def test_bsr3_small(grid, n):
-    """Reservoir-shaped 3x3-block systems (cond ~ 1e6), no preconditioner.  Rounding alone moves
-    the oracle's own iteration count widely here: over 24 perturbed runs, 1472-1659 (8x10x6),
-    2854-4058 (12x16x6, n = 8) and 2638-3453 (9x14x7) against 1482, 3116 and 2786, and its x_20 by
-    ~1e-6 on the 9x14x7 grid.  So these cases use bars derived from the oracle's spread over 24
-    perturbed runs (three understate it)."""
-    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), sensitive=True, n_perturb=24)
+RESERVOIR_GRIDS = [((8, 10, 6), 4), ((12, 16, 6), 8), ((9, 14, 7), 4)]
 
 
-@pytest.mark.parametrize("grid,n", [((8, 10, 6), 4), ((12, 16, 6), 8), ((9, 14, 7), 4)])
+@pytest.mark.parametrize("grid,n", RESERVOIR_GRIDS)
 def test_bsr3_block_jacobi(grid, n):
-    """Algorithm 7.1 with M = 3x3 block diagonal of A (right preconditioning) on the reservoir systems.
-    The iteration count still moves with rounding (over 24 perturbed oracle runs: 139-158 on 8x10x6,
-    153-173 on 9x14x7, always 165 on 12x16x6), so the bars use the spread of 24 runs."""
-    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), precond=1, sensitive=True, n_perturb=24)
+    """Reservoir-shaped 3x3-block systems with a larger diagonal term (accum 1: 50-56 iterations), Algorithm
+    7.1 with M = the 3x3 block diagonal of A from the right: strict bars (the oracle's count does not move
+    under rounding here)."""
+    check_parity(workloads.config3(n=n, grid=grid, maxit=8000, accum=1.0), precond=1)
+
+
+@pytest.mark.parametrize("grid,n", RESERVOIR_GRIDS)
+def test_bsr3_small(grid, n):
+    """The same systems without a preconditioner (822-1378 iterations).  Rounding alone moves the
+    oracle's count by up to 7% and puts its true residual at up to 1.0e-10, so the bars are widened to
+    its spread over 24 perturbed runs, within the caps (iterations 15%, iterates and x 1e-6)."""
+    check_parity(workloads.config3(n=n, grid=grid, maxit=8000, accum=1.0), mode="sensitive")
+
+
+@pytest.mark.parametrize("grid,n", RESERVOIR_GRIDS)
+def test_bsr3_block_jacobi_benchmark_conditioning(grid, n):
+    """The benchmark's conditioning (accum 1e-2, cond ~ 1e6) with block Jacobi: the oracle's count moves
+    by up to 17 under rounding (139-158 on 8x10x6, 153-173 on 9x14x7, always 165 on 12x16x6) and its
+    true residual reaches 2.3e-10, so widened bars within the caps."""
+    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), precond=1, mode="sensitive")
+
+
+@pytest.mark.parametrize("grid,n", RESERVOIR_GRIDS)
+def test_bsr3_chaotic(grid, n):
+    """The benchmark's conditioning without a preconditioner: rounding alone moves the oracle's own count
+    by up to 30% (1472-1659 on 8x10x6, 2854-4058 on 12x16x6 with n = 8, 2638-3453 on 9x14x7, over 24
+    perturbed runs) and its x_20 by up to 5e-6.  The count must lie within 15% of that range; the
+    iterates and x keep the 1e-6 caps; the true residual may not exceed the oracle's own largest."""
+    check_parity(workloads.config3(n=n, grid=grid, maxit=8000), mode="chaotic")
 
 
 @pytest.mark.parametrize("n", [1, 4])

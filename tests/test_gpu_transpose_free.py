@@ -18,7 +18,7 @@ import pytest
 import scipy.sparse as sp
 
 import workloads
-from tests.gpu_util import gpu_available, oracle_spread, rel, run_gpu, run_oracle
+from tests.gpu_util import check_against_bars, gpu_available, parity_bars, rel, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -30,27 +30,11 @@ import torch  # noqa: E402
 from paper_1106_3678_amd import binding  # noqa: E402
 
 
-def check_tf(p, K=20, x_tol=1e-6, sensitive=False, precond=0):
+def check_tf(p, K=20, x_tol=1e-6, mode="strict", precond=0):
     res, x, its = run_gpu(p, record=K, precond=precond, transpose_free=True)
     o = run_oracle(p, record=K, precond=precond, transpose_free=True)
-    it_tol, n_tol, res_tol = 1e-8, max(1, int(0.05 * o.iter)), p.tol + 1e-12
-    if sensitive:
-        s_it, s_n, s_true, s_x = oracle_spread(p, o, K, precond=precond, transpose_free=True, n_perturb=24)
-        it_tol = max(it_tol, 10 * s_it)
-        n_tol = max(n_tol, 2 * s_n)
-        res_tol = max(res_tol, 3 * s_true)
-        x_tol = max(x_tol, 10 * s_x)
-        print(f"  oracle spread: iterates {s_it:.2e} iterations {s_n} true residual {s_true:.2e} x {s_x:.2e}")
-    print(f"{p.name} (transpose-free): N={p.N} n={p.n} gpu flag={res.flag} iter={res.iter} "
-          f"err={res.err_recursive:.3e} true={res.err_true:.3e} | oracle flag={o.flag} iter={o.iter} err={o.err:.3e}",
-          flush=True)
-    assert res.flag == o.flag
-    assert abs(res.iter - o.iter) <= n_tol, (res.iter, o.iter, n_tol)
-    for k in range(min(K, o.iter, res.iter)):
-        assert rel(its[k], o.x_history[k]) < it_tol, (k + 1, rel(its[k], o.x_history[k]), it_tol)
-    if o.flag == 0:
-        assert res.err_true < res_tol, (res.err_true, res_tol)
-        assert rel(x, o.x) < x_tol, (rel(x, o.x), x_tol)
+    b = parity_bars(p, o, K, mode, precond=precond, transpose_free=True, x_tol=x_tol)
+    check_against_bars(" (transpose-free)", p, res, x, its, o, b, K)
     return res, x, o
 
 
@@ -77,11 +61,12 @@ def test_complex_small(n):
 
 @pytest.mark.parametrize("grid,n", [((8, 10, 6), 4), ((12, 16, 6), 8)])
 def test_bsr3_small(grid, n):
-    check_tf(workloads.config3(n=n, grid=grid), sensitive=True)
+    """Benchmark conditioning, no preconditioner: the oracle's own count is chaotic under rounding."""
+    check_tf(workloads.config3(n=n, grid=grid), mode="chaotic")
 
 
 def test_bsr3_block_jacobi():
-    check_tf(workloads.config3(n=4, grid=(8, 10, 6)), precond=1, sensitive=True)
+    check_tf(workloads.config3(n=4, grid=(8, 10, 6)), precond=1, mode="sensitive")
 
 
 @pytest.mark.parametrize("N", [4, 7, 12])
