@@ -206,8 +206,8 @@ def cpu_baseline(p, iters_gpu, sample_iters, bytes_per_iter, target_s=10.0, add_
             "algorithmic_gbs": bw, "bandwidth_frac": bw / add_gbs}
 
 
-def bench_serving(args, torch, workloads, binding):
-    """Continuous batching of a Poisson stream of uneven solves (fp32 inner / fp64 refinement, tol 1e-10)."""
+def serving_items(args, torch, workloads, binding):
+    """The serving trace's requests, generated and uploaded: (request, problem, A, b, x, Q) each."""
     reqs = workloads.serving_trace(count=args.requests)
     t = time.perf_counter()
     items = []
@@ -221,6 +221,13 @@ def bench_serving(args, torch, workloads, binding):
         if (k + 1) % 100 == 0:
             log(f"[bench] generated and uploaded {k + 1}/{len(reqs)} requests ({time.perf_counter() - t:.0f} s)")
     torch.cuda.synchronize()
+    return reqs, items
+
+
+def bench_serving(args, torch, workloads, binding, generated=None, sequential=True):
+    """Continuous batching of a Poisson stream of uneven solves (tol 1e-10; --serve-precision picks fp32
+    inner / fp64 refinement, as the serving configuration names, or fp64)."""
+    reqs, items = generated if generated is not None else serving_items(args, torch, workloads, binding)
     prec = binding.MLB_PREC_FP32_IR if args.serve_precision == "ir" else binding.MLB_PREC_FP64
     # warm-up: one request alone (first-use costs of the kernels)
     r0, p0, dA0, b0, x0, Q0 = items[0]
@@ -270,18 +277,20 @@ def bench_serving(args, torch, workloads, binding):
     log(f"[bench] saturated: {len(items)} requests in {saturated:.2f} s ({len(items) / saturated:.1f} solves/s)")
 
     # the same requests as plain fp64 solves, one after another
-    for it in items:
-        it[4].zero_()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    seq_err = 0.0
-    for r, p, dA, b, x, Q in items:
-        s = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit)
-        res = s.solve(b, x, Q)
-        s.close()
-        seq_err = max(seq_err, res.err_true)
-    seq = time.perf_counter() - t1
-    log(f"[bench] sequential plain fp64: {seq:.2f} s, max true residual {seq_err:.2e}")
+    seq, seq_err = float("nan"), float("nan")
+    if sequential:
+        for it in items:
+            it[4].zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        seq_err = 0.0
+        for r, p, dA, b, x, Q in items:
+            s = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit)
+            res = s.solve(b, x, Q)
+            s.close()
+            seq_err = max(seq_err, res.err_true)
+        seq = time.perf_counter() - t1
+        log(f"[bench] sequential plain fp64: {seq:.2f} s, max true residual {seq_err:.2e}")
     lat = np.array(lat)
     return {
         "metric": "batched solves/s", "value": len(items) / makespan, "unit": "solves/s", "n_gpus": 1,
@@ -301,6 +310,86 @@ def bench_serving(args, torch, workloads, binding):
         "saturated": {"seconds": saturated, "solves_per_s": len(items) / saturated,
                       "all_converged": bool(all(f == 0 for f in sat_flags))},
         "sequential_fp64": {"seconds": seq, "solves_per_s": len(items) / seq, "max_err_true": seq_err},
+    }
+
+
+def bench_serving_sequences(args, torch, workloads, binding):
+    """Serving with repeated matrices (Section 5.2 inside the server): `--matrices` systems drawn like the
+    serving trace's, each the A of a sequence of `--systems` right-hand sides; the requests arrive as a
+    Poisson stream at 200/s with the sequences interleaved at random.  Run twice on the same requests:
+    as sequences (one solver per A, A^H built once, n from 4 by the rule with step 2 in [2, 8]) and as
+    independent requests (create, solve, destroy each, n = 4)."""
+    g = np.random.default_rng(55)
+    base = workloads.serving_trace(count=args.matrices, n_min=args.seq_nmin)
+    t = time.perf_counter()
+    mats = []
+    for r in base:
+        p = workloads.serving_problem(r)
+        if p.n < 8:   # Q with 8 columns for the rule's n_max
+            p = workloads.serving_problem(workloads.Request(r.rid, r.arrival_s, r.dims, r.m, r.pe, 8, r.seed_stream))
+        mats.append((p, binding.to_device(p.A), binding.column_major(p.Q)))
+    order = np.repeat(np.arange(len(mats)), args.systems)
+    g.shuffle(order)
+    arrivals = np.cumsum(g.exponential(1 / 200.0, size=len(order)))
+    arrivals -= arrivals[0]
+    items = []
+    for k, mi in enumerate(order):
+        p, dA, Q = mats[mi]
+        b = torch.from_numpy(g.standard_normal(p.N)).cuda()
+        items.append((int(mi), float(arrivals[k]), b, torch.zeros(p.N, dtype=torch.float64, device="cuda")))
+    torch.cuda.synchronize()
+    log(f"[bench] {len(mats)} matrices, {len(items)} requests generated in {time.perf_counter() - t:.1f} s")
+
+    def run(as_sequences):
+        for it in items:
+            it[3].zero_()
+        torch.cuda.synchronize()
+        server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight,
+                                small_n_max=args.small_n_max)
+        t0 = time.perf_counter()
+        tickets = []
+        for mi, at, b, x in items:
+            delay = t0 + at - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            p, dA, Q = mats[mi]
+            if as_sequences:
+                tickets.append(server.submit_sequence(mi + 1, dA, b, x, Q, 4, 2, 8, 2, tol=p.tol, maxit=p.maxit))
+            else:
+                tickets.append(server.submit(dA, b, x, Q[:, :4], 4, tol=p.tol, maxit=p.maxit))
+        lat, flags, errs, ns = [], [], [], []
+        for tk in tickets:
+            res, tim = server.wait(tk)
+            lat.append(tim.latency_ms)
+            flags.append(res.flag)
+            errs.append(res.err_true)
+            ns.append(tim.n_used)
+        makespan = time.perf_counter() - t0
+        if as_sequences:
+            for mi in range(len(mats)):
+                server.end_sequence(mi + 1)
+        server.close()
+        lat = np.array(lat)
+        out = {"solves_per_s": len(items) / makespan, "makespan_s": makespan,
+               "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+               "all_converged": bool(all(f == 0 for f in flags)), "max_err_true": float(max(errs)),
+               "n_histogram": {int(v): int(c) for v, c in zip(*np.unique(ns, return_counts=True))}}
+        log(f"[bench] {'sequences' if as_sequences else 'independent'}: {out}")
+        return out
+
+    run(True)   # warm-up of both paths' kernels
+    seqs = run(True)
+    indep = run(False)
+    return {
+        "metric": "batched solves/s, sequences of systems", "value": seqs["solves_per_s"], "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": 1e3 * seqs["makespan_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving_sequences_{len(mats)}x{args.systems}", "matrices": len(mats),
+                   "N_range": [int(min(m[0].N for m in mats)), int(max(m[0].N for m in mats))],
+                   "systems_per_matrix": args.systems, "arrival_rate_per_s": 200.0, "inflight": args.inflight,
+                   "rule": "n from 4, step 2, in [2, 8]"},
+        "sequences": seqs, "independent_n4": indep,
+        "p50_ratio_independent_over_sequences": indep["latency_ms"]["p50"] / seqs["latency_ms"]["p50"],
     }
 
 
@@ -368,7 +457,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="convdiff3d",
-                    choices=["convdiff3d", "reservoir", "helmholtz", "serving", "sequence"])
+                    choices=["convdiff3d", "reservoir", "helmholtz", "serving", "sequence", "serving-seq"])
+    ap.add_argument("--matrices", type=int, default=200, help="serving-seq: matrices (sequences)")
+    ap.add_argument("--seq-nmin", type=float, default=1e3, help="serving-seq: smallest target N of the matrices")
     ap.add_argument("--systems", type=int, default=10, help="sequence: right-hand sides")
     ap.add_argument("--seq-matrix", default="convdiff3d", choices=["convdiff3d", "reservoir"],
                     help="sequence: the matrix (reservoir runs with block Jacobi)")
@@ -417,6 +508,9 @@ def main():
         return
     if args.workload == "sequence":
         print(json.dumps(bench_sequence(args, torch, workloads, binding)), flush=True)
+        return
+    if args.workload == "serving-seq":
+        print(json.dumps(bench_serving_sequences(args, torch, workloads, binding)), flush=True)
         return
     t = time.perf_counter()
     p, fmt, cplx, grid = make_problem(args.workload, workloads, args.n, args.m)
@@ -618,15 +712,19 @@ def secondary_workloads(args, torch, workloads, binding, dev):
             rec["ir_vs_fp64_time"] = rec["ir"]["ms_per_solve"] / rec["fp64"]["ms_per_solve"]
         out[name] = rec
     sargs = argparse.Namespace(**vars(args))
-    sargs.serve_precision = "ir"
     sargs.transpose_free = False
-    sv = bench_serving(sargs, torch, workloads, binding)
-    out["serving_ir"] = {"solves_per_s": sv["value"], "latency_ms": sv["latency_ms"], "config": sv["config"],
-                         "saturated_solves_per_s": sv["saturated"]["solves_per_s"],
-                         "sequential_fp64_solves_per_s": sv["sequential_fp64"]["solves_per_s"],
-                         "sequential_fp64_max_err_true": sv["sequential_fp64"]["max_err_true"],
-                         "speedup_saturated_vs_sequential_fp64": sv["saturated"]["solves_per_s"] /
-                         sv["sequential_fp64"]["solves_per_s"]}
+    generated = serving_items(sargs, torch, workloads, binding)
+    seq_rate = None
+    for prec in ("fp64", "ir"):
+        sargs.serve_precision = prec
+        sv = bench_serving(sargs, torch, workloads, binding, generated=generated, sequential=(prec == "fp64"))
+        if prec == "fp64":
+            seq_rate = sv["sequential_fp64"]["solves_per_s"]
+            out["serving_sequential_fp64"] = sv["sequential_fp64"]
+        out[f"serving_{prec}"] = {
+            "solves_per_s": sv["value"], "latency_ms": sv["latency_ms"], "config": sv["config"],
+            "dtype": sv["dtype"], "saturated_solves_per_s": sv["saturated"]["solves_per_s"],
+            "speedup_saturated_vs_sequential_fp64": sv["saturated"]["solves_per_s"] / seq_rate}
     return out
 
 

@@ -345,7 +345,8 @@ typedef struct {
   double queued_ms;         /* submit -> start                                  */
   double run_ms;            /* start -> completion                              */
   double latency_ms;        /* submit -> completion                             */
-  uint64_t footprint_bytes; /* admitted footprint                               */
+  uint64_t footprint_bytes; /* admitted footprint (a sequence's: of the whole sequence) */
+  int32_t n_used;           /* shadow vectors the solve ran with                */
 } mlb_request_timing;
 
 typedef struct {
@@ -373,6 +374,32 @@ int mlb_server_submit(mlb_server_handle s, const mlb_matrix* A, const mlb_option
  */
 int mlb_server_poll(mlb_server_handle s, int64_t ticket, mlb_result* res, mlb_request_timing* timing);
 int mlb_server_wait(mlb_server_handle s, int64_t ticket, mlb_result* res, mlb_request_timing* timing);
+
+/*
+ * Sequences of systems inside the server (Section 5.2: the method is at its
+ * strongest over a sequence of systems, with n chosen automatically from one
+ * system to the next).  Requests submitted with the same nonzero key form a
+ * sequence: they must name the same A (the same device arrays, unchanged until
+ * the sequence ends) and the same options and rule, and are solved one at a
+ * time in submission order by one solver the sequence owns -- A^H is built
+ * once, with the first request, and the workspace (sized for n_max) is reused.
+ * The first request runs with opt->n; after each request the next n follows
+ * mlb_sequence_next_n with the solve times of the previous and the current
+ * request (timing->n_used reports it).  Each result is bitwise that of a fresh
+ * create + solve with that n.  Q is N x n_max (column-major, ldq >= N), of
+ * which the first n columns are used.  The sequence's footprint
+ * (mlbicgstab_workspace_size with n = n_max) is admitted with its first
+ * request and held until mlb_server_end_sequence; other requests keep flowing
+ * meanwhile.  Errors as mlb_server_submit; MLB_EINVAL for key 0, for an A,
+ * options or rule that differ from the sequence's, or for an ended sequence.
+ */
+int mlb_server_submit_sequence(mlb_server_handle s, uint64_t key, const mlb_matrix* A, const mlb_options* opt,
+                               int32_t n_min, int32_t n_max, int32_t step, const void* b, void* x, const void* Q,
+                               int64_t ldq, int64_t* ticket);
+
+/* End a sequence: no more requests may join it; its solver and footprint are
+ * released once its queued requests have run.  MLB_EINVAL for an unknown key. */
+int mlb_server_end_sequence(mlb_server_handle s, uint64_t key);
 
 /* Budget, peak footprint in flight, queue length, peak concurrency, completions. */
 int mlb_server_stats(mlb_server_handle s, mlb_server_stats_t* out);

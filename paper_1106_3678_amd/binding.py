@@ -78,6 +78,7 @@ class mlb_request_timing(ctypes.Structure):
         ("run_ms", ctypes.c_double),
         ("latency_ms", ctypes.c_double),
         ("footprint_bytes", ctypes.c_uint64),
+        ("n_used", ctypes.c_int32),
     ]
 
 
@@ -145,6 +146,13 @@ _lib.mlb_server_submit.argtypes = [mlb_server_handle, ctypes.POINTER(mlb_matrix)
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                    ctypes.POINTER(ctypes.c_int64)]
 _lib.mlb_server_submit.restype = ctypes.c_int
+_lib.mlb_server_submit_sequence.argtypes = [mlb_server_handle, ctypes.c_uint64, ctypes.POINTER(mlb_matrix),
+                                            ctypes.POINTER(mlb_options), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+_lib.mlb_server_submit_sequence.restype = ctypes.c_int
+_lib.mlb_server_end_sequence.argtypes = [mlb_server_handle, ctypes.c_uint64]
+_lib.mlb_server_end_sequence.restype = ctypes.c_int
 for _f in ("mlb_server_poll", "mlb_server_wait"):
     getattr(_lib, _f).argtypes = [mlb_server_handle, ctypes.c_int64, ctypes.POINTER(mlb_result),
                                   ctypes.POINTER(mlb_request_timing)]
@@ -263,6 +271,19 @@ def mlb_server_submit(s, A: mlb_matrix, opt: mlb_options, b_ptr: int, x_ptr: int
                                   ctypes.c_void_p(x_ptr), ctypes.c_void_p(q_ptr), ctypes.c_int64(ldq),
                                   ctypes.byref(t)))
     return t.value
+
+
+def mlb_server_submit_sequence(s, key: int, A: mlb_matrix, opt: mlb_options, n_min: int, n_max: int, step: int,
+                               b_ptr: int, x_ptr: int, q_ptr: int, ldq: int) -> int:
+    t = ctypes.c_int64()
+    _check(_lib.mlb_server_submit_sequence(s, ctypes.c_uint64(key), ctypes.byref(A), ctypes.byref(opt), n_min, n_max,
+                                           step, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr),
+                                           ctypes.c_void_p(q_ptr), ctypes.c_int64(ldq), ctypes.byref(t)))
+    return t.value
+
+
+def mlb_server_end_sequence(s, key: int) -> int:
+    return _check(_lib.mlb_server_end_sequence(s, ctypes.c_uint64(key)))
 
 
 def mlb_server_poll(s, ticket: int):
@@ -485,6 +506,23 @@ class Server:
         t = mlb_server_submit(self.h, dmat.descriptor(), opt, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
         self._keep[t] = (dmat, b, x, Q)
         return t
+
+    def submit_sequence(self, key: int, dmat: DeviceMatrix, b, x, Q, n: int, n_min: int, n_max: int, step: int,
+                        tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0, precision: int = MLB_PREC_FP64,
+                        inner_tol: float = 0.0, precond: int = MLB_PRECOND_NONE, transpose_free: bool = False,
+                        order: int = MLB_ORDER_FUSED) -> int:
+        """A request of sequence `key` (same A throughout; Q is N x n_max, n is the first request's)."""
+        N = dmat.nrows
+        ldq = q_layout(Q, N, n_max)
+        opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, 0, 0, None, precond, int(transpose_free),
+                          order)
+        t = mlb_server_submit_sequence(self.h, key, dmat.descriptor(), opt, n_min, n_max, step, b.data_ptr(),
+                                       x.data_ptr(), Q.data_ptr(), ldq)
+        self._keep[t] = (dmat, b, x, Q)
+        return t
+
+    def end_sequence(self, key: int) -> None:
+        mlb_server_end_sequence(self.h, key)
 
     def wait(self, ticket: int):
         try:

@@ -1245,6 +1245,21 @@ static void set_active_n(mlb_solver* h, int n) {
   }
 }
 
+// Moves a solver's work (and the stream-ordered frees of its buffers) to stream
+// s; the caller has synchronised the old stream.  Serving sequences run their
+// solver on whichever worker takes the next request.
+static void set_stream(mlb_solver* h, hipStream_t s) {
+  h->s = s;
+  h->al.stream = s;
+  if (h->real) {
+    h->real->e64.s = s;
+    if (h->real->has32) h->real->e32.s = s;
+  } else {
+    h->cpx->e64.s = s;
+    if (h->cpx->has32) h->cpx->e32.s = s;
+  }
+}
+
 static int solve_solver(mlb_solver* h, const void* b, void* x, const void* Q, int64_t ldq, mlb_result* res) {
   if (!b || !x || !Q) throw Error{MLB_EINVAL, "b, x and Q must be device pointers"};
   if (ldq < h->N) throw Error{MLB_EINVAL, "ldq must be >= N"};
@@ -1275,10 +1290,12 @@ static void launch_small(const SmallJob<V64, typename traits<V64>::wide>* dj, in
 
 // Runs the systems of hs (same dtype, same stream) in one launch of k_small and
 // fills res[k] as mlbicgstab_solve would.
+// job_buf: a device buffer for at least `count` job descriptors, or NULL to
+// allocate one for the call (the serving batchers keep one each).
 template <class V64, class V32>
 static void batch_impl(mlb_solver* const* hs, int count, const void* const* b, void* const* x,
                        const void* const* Q, const int64_t* ldq, mlb_result* res,
-                       Impl<V64, V32>* (*impl_of)(mlb_solver*)) {
+                       Impl<V64, V32>* (*impl_of)(mlb_solver*), void* job_buf) {
   using Sc = typename traits<V64>::wide;
   hipStream_t s = hs[0]->s;
   std::vector<SmallJob<V64, Sc>> jobs((size_t)count);
@@ -1316,7 +1333,7 @@ static void batch_impl(mlb_solver* const* hs, int count, const void* const* b, v
     nb = std::max(nb, bucket(e.n));
   }
   Allocs tmp(s, false);
-  auto* dj = tmp.get<SmallJob<V64, Sc>>((size_t)count);
+  auto* dj = job_buf ? (SmallJob<V64, Sc>*)job_buf : tmp.get<SmallJob<V64, Sc>>((size_t)count);
   HIP_TRY(hipMemcpyAsync(dj, jobs.data(), sizeof(SmallJob<V64, Sc>) * count, hipMemcpyHostToDevice, s));
   hipEvent_t t0, t1;
   HIP_TRY(hipEventCreate(&t0));
@@ -1358,7 +1375,7 @@ static Impl<double, float>* real_impl(mlb_solver* h) { return h->real.get(); }
 static Impl<cplx<double>, cplx<float>>* cplx_impl(mlb_solver* h) { return h->cpx.get(); }
 
 static int solve_batch(mlb_solver* const* hs, int count, const void* const* b, void* const* x, const void* const* Q,
-                       const int64_t* ldq, mlb_result* res) {
+                       const int64_t* ldq, mlb_result* res, void* job_buf = nullptr) {
   if (!hs || !b || !x || !Q || !ldq) throw Error{MLB_EINVAL, "handles, b, x, Q and ldq must be non-NULL"};
   if (count < 1 || count > MLB_BATCH_MAX) throw Error{MLB_EINVAL, "count must be in [1, MLB_BATCH_MAX]"};
   for (int k = 0; k < count; ++k) {
@@ -1370,9 +1387,9 @@ static int solve_batch(mlb_solver* const* hs, int count, const void* const* b, v
     check_batchable(hs[k]);
   }
   if (hs[0]->real)
-    batch_impl(hs, count, b, x, Q, ldq, res, real_impl);
+    batch_impl(hs, count, b, x, Q, ldq, res, real_impl, job_buf);
   else
-    batch_impl(hs, count, b, x, Q, ldq, res, cplx_impl);
+    batch_impl(hs, count, b, x, Q, ldq, res, cplx_impl, job_buf);
   return 0;
 }
 
@@ -1645,6 +1662,8 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+struct SeqEntry;
+
 struct Request {
   int64_t ticket = 0;
   mlb_matrix A{};
@@ -1660,6 +1679,27 @@ struct Request {
   std::string err;
   bool done = false;
   bool small = false;   // solved by a batcher (one workgroup per system)
+  std::shared_ptr<SeqEntry> seq;   // the sequence it belongs to, or null
+  int32_t n_used = 0;              // shadow vectors it ran with
+};
+
+// A sequence of systems with one A inside the server (Section 5.2): one solver
+// (A^H, workspace for n_max) serves every request of the sequence, one request
+// at a time in submission order, and n follows the rule of mlb_sequence_next_n
+// from one request to the next.  Its footprint is admitted with its first
+// request and held until the sequence ends.
+struct SeqEntry {
+  uint64_t key = 0;
+  mlb_matrix A{};
+  mlb_options opt{};
+  int32_t n_min = 1, n_max = 1, step = 0, n_next = 1;
+  double t_prev = -1.0;
+  std::unique_ptr<mlb_solver> h;
+  size_t footprint = 0;
+  bool admitted = false;   // footprint counted in the server's used bytes
+  bool busy = false;       // a worker is running one of its requests
+  bool ending = false;     // mlb_server_end_sequence was called
+  std::deque<std::shared_ptr<Request>> pending;   // taken while busy, in order
 };
 
 struct Server {
@@ -1673,6 +1713,7 @@ struct Server {
   std::deque<std::shared_ptr<Request>> small_queue;  // requests for the batchers
   int small_n_max = 0;                                // largest N a batcher takes (0: none)
   std::unordered_map<int64_t, std::shared_ptr<Request>> table;
+  std::unordered_map<uint64_t, std::shared_ptr<SeqEntry>> seqs;   // live sequences by key
   int64_t next_ticket = 1;
   int64_t completed = 0;
   bool stopping = false;
@@ -1696,6 +1737,55 @@ static void run_request(Request& r, hipStream_t st, int* flags) {
   }
 }
 
+// One request of a sequence on this worker's stream: the sequence's solver is
+// created with its first request (own done flag, workspace for n_max) and moved
+// to the stream of whichever worker runs the next one.
+static void run_seq_request(SeqEntry& q, Request& r, hipStream_t st) {
+  try {
+    if (!q.h) {
+      mlb_options o = q.opt;
+      o.n = q.n_max;
+      q.h = create_solver(&q.A, &o, st, true, nullptr);
+    }
+    set_stream(q.h.get(), st);
+    set_active_n(q.h.get(), q.n_next);
+    r.n_used = q.n_next;
+    r.rc = solve_solver(q.h.get(), r.b, r.x, r.Q, r.ldq, &r.res);
+    HIP_TRY(hipStreamSynchronize(st));
+    const double t = r.res.solve_ms;
+    q.n_next = mlb_sequence_next_n(r.n_used, q.t_prev, t, q.step, q.n_min, q.n_max);
+    q.t_prev = t;
+    set_stream(q.h.get(), nullptr);   // idle: frees, if any, go to the legacy stream
+  } catch (const Error& e) {
+    r.rc = e.code;
+    r.err = e.msg;
+  } catch (const std::exception& e) {
+    r.rc = MLB_EHIP;
+    r.err = e.what();
+  }
+}
+
+// Whether the head request of the worker queue may start now.
+static bool head_fits(const Server* S) {
+  const Request& r = *S->queue.front();
+  if (r.seq) return r.seq->busy || r.seq->admitted || S->used + r.seq->footprint <= S->budget;
+  return S->used + r.footprint <= S->budget;
+}
+
+// Whether a request of sequence q still waits in the worker queue.
+static bool seq_queued(const Server* S, const std::shared_ptr<SeqEntry>& q) {
+  for (auto& r : S->queue)
+    if (r->seq == q) return true;
+  return false;
+}
+
+// Frees a finished sequence's solver (called without the server lock).
+static void drop_sequence(std::shared_ptr<SeqEntry>& q) {
+  if (!q || !q->h) return;
+  (void)hipStreamSynchronize(q->h->s);
+  q->h.reset();
+}
+
 static void worker_main(Server* S) {
   hipStream_t st = nullptr;
   int* flags = nullptr;
@@ -1705,36 +1795,71 @@ static void worker_main(Server* S) {
     std::shared_ptr<Request> r;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] {
-        return (S->stopping && S->queue.empty()) ||
-               (!S->queue.empty() && S->used + S->queue.front()->footprint <= S->budget);
-      });
-      if (S->queue.empty()) break;   // stopping and drained
-      r = S->queue.front();
-      S->queue.pop_front();
-      S->used += r->footprint;
+      while (true) {
+        S->cv_work.wait(lk, [&] { return (S->stopping && S->queue.empty()) || (!S->queue.empty() && head_fits(S)); });
+        if (S->queue.empty()) break;   // stopping and drained
+        r = S->queue.front();
+        S->queue.pop_front();
+        if (r->seq && r->seq->busy) {   // its sequence runs on another worker, which takes it next
+          r->seq->pending.push_back(r);
+          r.reset();
+          continue;
+        }
+        break;
+      }
+      if (!r) break;
+      if (r->seq) {
+        r->seq->busy = true;
+        if (!r->seq->admitted) {
+          S->used += r->seq->footprint;
+          r->seq->admitted = true;
+        }
+      } else {
+        S->used += r->footprint;
+      }
       S->peak = std::max(S->peak, S->used);
       S->running++;
       S->peak_running = std::max(S->peak_running, S->running);
       r->t_start = now_s();
     }
     S->cv_work.notify_all();   // the next head may fit too
-    if (ok) {
-      run_request(*r, st, flags);
-    } else {
-      r->rc = MLB_EHIP;
-      r->err = "serving worker could not create its stream or pinned flags";
+    while (r) {
+      std::shared_ptr<SeqEntry> q = r->seq, finished;
+      if (!ok) {
+        r->rc = MLB_EHIP;
+        r->err = "serving worker could not create its stream or pinned flags";
+      } else if (q) {
+        run_seq_request(*q, *r, st);
+      } else {
+        run_request(*r, st, flags);
+      }
+      std::shared_ptr<Request> next;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->t_done = now_s();
+        r->done = true;
+        if (!q) S->used -= r->footprint;
+        S->running--;
+        S->completed++;
+        if (q && !q->pending.empty()) {   // the sequence's next request, on this worker
+          next = q->pending.front();
+          q->pending.pop_front();
+          S->running++;
+          next->t_start = now_s();
+        } else if (q) {
+          q->busy = false;
+          if (q->ending && !seq_queued(S, q)) {
+            S->used -= q->footprint;
+            S->seqs.erase(q->key);
+            finished = q;
+          }
+        }
+      }
+      S->cv_work.notify_all();
+      S->cv_done.notify_all();
+      drop_sequence(finished);
+      r = next;
     }
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      r->t_done = now_s();
-      r->done = true;
-      S->used -= r->footprint;
-      S->running--;
-      S->completed++;
-    }
-    S->cv_work.notify_all();
-    S->cv_done.notify_all();
   }
   if (flags) (void)hipHostFree(flags);
   if (st) (void)hipStreamDestroy(st);
@@ -1751,8 +1876,12 @@ constexpr int N_BATCHERS = 2;
 static void batcher_main(Server* S) {
   hipStream_t st = nullptr;
   int* flags = nullptr;
+  void* jobs = nullptr;   // job descriptors of one batch, kept for the batcher's life
+  const size_t job_bytes = BATCH_CAP * std::max(sizeof(SmallJob<double, double>),
+                                                sizeof(SmallJob<cplx<double>, cplx<double>>));
   bool ok = hipSetDevice(S->device) == hipSuccess && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
-            hipHostMalloc((void**)&flags, 2 * BATCH_CAP * sizeof(int), hipHostMallocMapped) == hipSuccess;
+            hipHostMalloc((void**)&flags, 2 * BATCH_CAP * sizeof(int), hipHostMallocMapped) == hipSuccess &&
+            hipMalloc(&jobs, job_bytes) == hipSuccess;
   while (true) {
     std::vector<std::shared_ptr<Request>> batch;
     {
@@ -1825,7 +1954,7 @@ static void batcher_main(Server* S) {
         if (part.empty()) continue;
         std::vector<mlb_result> res(part.size());
         try {
-          solve_batch(part.data(), (int)part.size(), pb.data(), px.data(), pq.data(), pl.data(), res.data());
+          solve_batch(part.data(), (int)part.size(), pb.data(), px.data(), pq.data(), pl.data(), res.data(), jobs);
           for (size_t q = 0; q < part.size(); ++q) {
             batch[pi[q]]->res = res[q];
             batch[pi[q]]->rc = res[q].flag;
@@ -1859,6 +1988,7 @@ static void batcher_main(Server* S) {
     S->cv_work.notify_all();
     S->cv_done.notify_all();
   }
+  if (jobs) (void)hipFree(jobs);
   if (flags) (void)hipHostFree(flags);
   if (st) (void)hipStreamDestroy(st);
 }
@@ -1868,7 +1998,8 @@ static void fill_timing(const Request& r, mlb_request_timing* t) {
   t->queued_ms = 1e3 * (r.t_start - r.t_submit);
   t->run_ms = 1e3 * (r.t_done - r.t_start);
   t->latency_ms = 1e3 * (r.t_done - r.t_submit);
-  t->footprint_bytes = r.footprint;
+  t->footprint_bytes = r.seq ? r.seq->footprint : r.footprint;
+  t->n_used = r.n_used ? r.n_used : r.opt.n;
 }
 
 }  // namespace mlb
@@ -1941,6 +2072,103 @@ int mlb_server_submit(mlb_server_handle S, const mlb_matrix* A, const mlb_option
   });
 }
 
+static bool same_matrix(const mlb_matrix& a, const mlb_matrix& b) {
+  return a.format == b.format && a.dtype == b.dtype && a.nrows == b.nrows && a.nnz == b.nnz && a.row_ptr == b.row_ptr &&
+         a.col_idx == b.col_idx && a.values == b.values;
+}
+
+static bool same_options_but_n(const mlb_options& a, const mlb_options& b) {
+  return a.tol == b.tol && a.maxit == b.maxit && a.kappa == b.kappa && a.precision == b.precision &&
+         a.inner_tol == b.inner_tol && a.max_outer == b.max_outer && a.precond == b.precond &&
+         a.transpose_free == b.transpose_free && a.order == b.order;
+}
+
+int mlb_server_submit_sequence(mlb_server_handle S, uint64_t key, const mlb_matrix* A, const mlb_options* opt,
+                               int32_t n_min, int32_t n_max, int32_t step, const void* b, void* x, const void* Q,
+                               int64_t ldq, int64_t* ticket) {
+  return guarded([&]() -> int {
+    if (!S || !ticket) throw Error{MLB_EINVAL, "server and ticket must be non-NULL"};
+    if (key == 0) throw Error{MLB_EINVAL, "the sequence key must be nonzero"};
+    check_matrix(A);
+    check_options(opt);
+    if (opt->record_iterates > 0) throw Error{MLB_EINVAL, "a sequence records no iterates"};
+    if (n_max > MLB_MAX_N) throw Error{MLB_EUNSUPPORTED, "n_max > MLB_MAX_N (32) is not supported"};
+    if (step < 0 || n_min < 1 || n_max < n_min || opt->n < n_min || opt->n > n_max)
+      throw Error{MLB_EINVAL, "need step >= 0 and 1 <= n_min <= opt->n <= n_max"};
+    if (!b || !x || !Q) throw Error{MLB_EINVAL, "b, x and Q must be device pointers"};
+    if (ldq < A->nrows) throw Error{MLB_EINVAL, "ldq must be >= N"};
+    mlb_options o = *opt;
+    o.n = n_max;
+    size_t fp = 0;
+    int rc = mlbicgstab_workspace_size(A, &o, &fp);
+    if (rc != 0) throw Error{rc, g_last_error};
+    if (fp > S->budget) throw Error{MLB_ENOMEM, "the sequence's footprint exceeds the server's HBM budget"};
+    auto r = std::make_shared<Request>();
+    r->A = *A;
+    r->opt = *opt;
+    r->b = b;
+    r->x = x;
+    r->Q = Q;
+    r->ldq = ldq;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->stopping) throw Error{MLB_EINVAL, "server is shutting down"};
+      auto it = S->seqs.find(key);
+      std::shared_ptr<SeqEntry> q;
+      if (it == S->seqs.end()) {
+        q = std::make_shared<SeqEntry>();
+        q->key = key;
+        q->A = *A;
+        q->opt = *opt;
+        q->n_min = n_min;
+        q->n_max = n_max;
+        q->step = step;
+        q->n_next = opt->n;
+        q->footprint = fp;
+        S->seqs[key] = q;
+      } else {
+        q = it->second;
+        if (q->ending) throw Error{MLB_EINVAL, "the sequence has been ended"};
+        if (!same_matrix(q->A, *A)) throw Error{MLB_EINVAL, "a sequence keeps one A (the same device arrays)"};
+        if (!same_options_but_n(q->opt, *opt) || q->n_min != n_min || q->n_max != n_max || q->step != step)
+          throw Error{MLB_EINVAL, "a sequence keeps its options and its rule for n"};
+      }
+      r->seq = q;
+      r->ticket = S->next_ticket++;
+      r->t_submit = now_s();
+      S->table[r->ticket] = r;
+      S->queue.push_back(r);
+      *ticket = r->ticket;
+    }
+    S->cv_work.notify_all();
+    return 0;
+  });
+}
+
+int mlb_server_end_sequence(mlb_server_handle S, uint64_t key) {
+  return guarded([&]() -> int {
+    if (!S) throw Error{MLB_EINVAL, "server is NULL"};
+    std::shared_ptr<SeqEntry> finished;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      auto it = S->seqs.find(key);
+      if (it == S->seqs.end()) throw Error{MLB_EINVAL, "no live sequence with this key"};
+      auto q = it->second;
+      q->ending = true;
+      // requests of the sequence still queued keep it alive; the worker that
+      // finishes the last one releases it
+      if (!q->busy && q->pending.empty() && !seq_queued(S, q)) {
+        if (q->admitted) S->used -= q->footprint;
+        S->seqs.erase(it);
+        finished = q;
+      }
+    }
+    drop_sequence(finished);
+    S->cv_work.notify_all();
+    return 0;
+  });
+}
+
 static int collect(mlb_server_handle S, int64_t ticket, mlb_result* res, mlb_request_timing* t, bool block) {
   std::shared_ptr<Request> r;
   {
@@ -1999,6 +2227,8 @@ int mlb_server_destroy(mlb_server_handle S) {
     S->cv_work.notify_all();
     for (auto& w : S->workers) w.join();
     for (auto& w : S->batchers) w.join();
+    for (auto& kv : S->seqs) drop_sequence(kv.second);   // sequences never ended
+    S->seqs.clear();
     delete S;
     return 0;
   });

@@ -169,3 +169,76 @@ def test_one_request_matches_oracle():
     assert res.flag == o.flag == 0
     assert abs(res.iter - o.iter) <= max(1, int(0.05 * o.iter))
     assert rel(x.cpu().numpy(), o.x) < 1e-6
+
+
+def test_sequence_in_server_follows_the_rule_and_matches_fresh_solves():
+    """Section 5.2 inside the server: the requests of a sequence share one solver (A^H built once) and
+    run in submission order while other requests flow; n follows mlb_sequence_next_n replayed from
+    the reported solve times, and each result is bitwise a fresh create + solve with that n."""
+    n0, n_min, n_max, step = 4, 2, 8, 2
+    p = workloads.config2(n=n_max, m=20, maxit=4000)
+    g = np.random.default_rng(77)
+    rhs = [g.standard_normal(p.N) for _ in range(7)]
+    dA = binding.to_device(p.A)
+    Q = binding.column_major(p.Q)
+    bs = [torch.from_numpy(v).cuda() for v in rhs]
+    xs = [torch.zeros(p.N, dtype=torch.float64, device="cuda") for _ in rhs]
+    others = requests(count=6, seed=9)
+    obufs = [upload(q) for q, _ in others]
+    torch.cuda.synchronize()
+    server = binding.Server(budget_bytes=8 << 30, max_inflight=3)
+    key = 0x5EC
+    tickets, otickets = [], []
+    for k, (b, x) in enumerate(zip(bs, xs)):
+        tickets.append(server.submit_sequence(key, dA, b, x, Q, n0, n_min, n_max, step, tol=p.tol, maxit=p.maxit))
+        if k < len(others):
+            (q, prec), (qA, qb, qx, qQ) = others[k], obufs[k]
+            otickets.append(server.submit(qA, qb, qx, qQ, q.n, tol=q.tol, maxit=q.maxit, precision=prec))
+    results = [server.wait(t) for t in tickets]
+    for t in otickets:
+        res, _ = server.wait(t)
+        assert res.flag == 0
+    server.end_sequence(key)
+    st = server.stats()
+    server.close()
+    assert st.used_bytes == 0
+    used = [tim.n_used for _, tim in results]
+    times = [res.solve_ms for res, _ in results]
+    print("n used:", used, "solve ms:", [round(t, 2) for t in times], "iterations:", [r.iter for r, _ in results],
+          flush=True)
+    n, t_prev = n0, -1.0
+    for k in range(len(rhs)):
+        assert used[k] == n, (k, used, n)
+        n_next = binding.mlb_sequence_next_n(n, t_prev, times[k], step, n_min, n_max)
+        t_prev, n = times[k], n_next
+    for (res, tim), b, x in zip(results, bs, xs):
+        assert res.flag == 0
+        xf = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+        s = binding.Solver(dA, tim.n_used, tol=p.tol, maxit=p.maxit)
+        rf = s.solve(b, xf, Q[:, :tim.n_used])
+        s.close()
+        assert rf.iter == res.iter and rf.flag == res.flag
+        assert torch.equal(xf, x)
+
+
+def test_sequence_argument_errors():
+    p = workloads.config1(n=4)
+    dA, b, x, Q = upload(p)
+    dB = binding.to_device(p.A)
+    server = binding.Server(budget_bytes=1 << 30, max_inflight=1)
+    try:
+        with pytest.raises(binding.MlbError):
+            server.submit_sequence(0, dA, b, x, Q, 4, 2, 4, 1)          # key 0
+        t = server.submit_sequence(7, dA, b, x, Q, 4, 2, 4, 1)
+        with pytest.raises(binding.MlbError):
+            server.submit_sequence(7, dB, b, x, Q, 4, 2, 4, 1)          # another A
+        with pytest.raises(binding.MlbError):
+            server.submit_sequence(7, dA, b, x, Q, 4, 2, 4, 2)          # another rule
+        res, tim = server.wait(t)
+        assert res.flag == 0 and tim.n_used == 4
+        server.end_sequence(7)
+        with pytest.raises(binding.MlbError):
+            server.end_sequence(7)                                     # already ended
+        assert server.stats().used_bytes == 0
+    finally:
+        server.close()
