@@ -478,8 +478,8 @@ def main():
                     help="recurrence order: Gram-matrix form (fused) or the sequential loops (literal)")
     ap.add_argument("--transpose-free", action="store_true",
                     help="iterate without A^H (beta recurrence from q_s^H A g, w recombined)")
-    ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi"],
-                    help="auto: block Jacobi for the reservoir workload, none otherwise")
+    ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi", "ilu0"],
+                    help="auto: block Jacobi for the reservoir workload, none otherwise; ilu0: ILU(0)")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="cap on the oracle sample (iterations); 0: about 15 s of CPU time")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
@@ -526,7 +526,9 @@ def main():
     nbrows = len(p.A.indptr) - 1
     log(f"[bench] generated {p.name}: N={p.N} stored={nnz} in {time.perf_counter() - t:.1f} s")
     use_jacobi = args.precond == "jacobi" or (args.precond == "auto" and args.workload == "reservoir")
-    run = timed_solves(torch, binding, p, dev, args.precision, use_jacobi, args.transpose_free, args.order,
+    precond = binding.MLB_PRECOND_ILU0 if args.precond == "ilu0" else \
+        binding.MLB_PRECOND_JACOBI if use_jacobi else binding.MLB_PRECOND_NONE
+    run = timed_solves(torch, binding, p, dev, args.precision, precond, args.transpose_free, args.order,
                        args.steps, args.warmup, args.inner_tol, keep_solver=True)
     solver = run.pop("solver")
     ms, last = run["ms"], run["last"]
@@ -584,7 +586,8 @@ def main():
             "n": p.n,
             "tol": p.tol,
             "precision": args.precision,
-            "preconditioner": "block Jacobi (right)" if use_jacobi else "none",
+            "preconditioner": {binding.MLB_PRECOND_ILU0: "ILU(0) (right)", binding.MLB_PRECOND_JACOBI:
+                               "block Jacobi (right)"}.get(precond, "none"),
             "variant": "transpose-free (no A^H)" if args.transpose_free else "Algorithm 7.1 (explicit A^H)",
             "recurrence_order": args.order,
             "iterations": int(last.iter),
@@ -637,7 +640,7 @@ def make_problem(workload, workloads, n=0, m=0):
 dA_keep = []
 
 
-def timed_solves(torch, binding, p, dev, precision, jacobi, transpose_free, order, steps, warmup, inner_tol=0.0,
+def timed_solves(torch, binding, p, dev, precision, precond, transpose_free, order, steps, warmup, inner_tol=0.0,
                  keep_solver=False):
     """Upload p, create a solver, run `warmup` untimed and `steps` timed solves from x_0 = 0 (bracketed by
     device synchronisations); returns ms per solve, the last result and the solver set-up time."""
@@ -652,8 +655,7 @@ def timed_solves(torch, binding, p, dev, precision, jacobi, transpose_free, orde
     torch.cuda.synchronize()
     t_create = time.perf_counter()
     solver = binding.Solver(dA, p.n, tol=p.tol, maxit=p.maxit, precision=prec, inner_tol=inner_tol,
-                            precond=binding.MLB_PRECOND_JACOBI if jacobi else binding.MLB_PRECOND_NONE,
-                            transpose_free=transpose_free,
+                            precond=int(precond), transpose_free=transpose_free,
                             order=binding.MLB_ORDER_LITERAL if order == "literal" else binding.MLB_ORDER_FUSED)
     torch.cuda.synchronize()
     create_ms = 1e3 * (time.perf_counter() - t_create)   # validation, A^H (and M^{-1} / fp32 copies)
@@ -697,7 +699,9 @@ def secondary_workloads(args, torch, workloads, binding, dev):
         rec = {"N": p.N, "n": p.n, "format": fmt, "preconditioner": "block Jacobi (right)" if wl == "reservoir" else
                "none", "steps": args.extra_steps, "warmup": 1}
         for prec in precs:
-            r = timed_solves(torch, binding, p, dev, prec, wl == "reservoir", False, "fused", args.extra_steps, 1)
+            r = timed_solves(torch, binding, p, dev, prec,
+                             binding.MLB_PRECOND_JACOBI if wl == "reservoir" else binding.MLB_PRECOND_NONE,
+                             False, "fused", args.extra_steps, 1)
             last = r["last"]
             e = {"ms_per_solve": r["ms"], "iterations": int(last.iter), "flag": int(last.flag),
                  "err_true": last.err_true, "outer_iters": int(last.outer_iters), "fp64_iters": int(last.fp64_iters)}

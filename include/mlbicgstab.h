@@ -50,7 +50,7 @@ enum {
 enum { MLB_R64 = 0, MLB_C128 = 1 };          /* value type of A, b, x, Q        */
 enum { MLB_CSR = 0, MLB_BSR3 = 1 };          /* storage of A                     */
 enum { MLB_PREC_FP64 = 0, MLB_PREC_FP32_IR = 1 };
-enum { MLB_PRECOND_NONE = 0, MLB_PRECOND_JACOBI = 1 };
+enum { MLB_PRECOND_NONE = 0, MLB_PRECOND_JACOBI = 1, MLB_PRECOND_ILU0 = 2 };
 
 #define MLB_MAX_N 32                          /* largest number of shadow vectors */
 
@@ -107,6 +107,18 @@ typedef struct {
  * MLB_EINVAL if a (block) row has no stored diagonal entry or a singular one.
  * MLB_PRECOND_NONE (0) is M = I, Algorithm 4.1.
  *
+ * precond = MLB_PRECOND_ILU0 runs Algorithm 7.1 with M = ILU(0) of A, the
+ * preconditioner of the paper's experiments (Section 5): M = L U with L unit
+ * lower and U upper triangular (by 3x3 blocks for BSR3), both on A's pattern,
+ * and (L U)_ij = a_ij wherever A is stored.  Applied from the right as above:
+ * every product with A is preceded by M^{-1} (two triangular solves), and
+ * f_s = M^{-H} A^H q_s.  create() factors A on the device (one launch per
+ * level of the row dependencies; the level sets come from a host pass over a
+ * copy of A's index arrays) and fails with MLB_EINVAL for a (block) row without
+ * a stored diagonal, a column stored twice in a row, or a zero / singular
+ * pivot.  The triangular solves take one launch per level: 3m - 2 levels each
+ * on an m^3 7-point grid.  fp64 only (MLB_EUNSUPPORTED with MLB_PREC_FP32_IR).
+ *
  * transpose_free = 1 runs the iteration without A^H (an addition of this
  * library; Section 4 names A^H-free algorithms but prints only their costs).
  * The beta recurrence of step 2 of Algorithm 4.1 needs
@@ -130,7 +142,7 @@ typedef struct {
   int32_t max_outer;
   int32_t record_iterates;
   void* iterates;           /* device, N x record_iterates, or NULL            */
-  int32_t precond;          /* MLB_PRECOND_NONE or MLB_PRECOND_JACOBI          */
+  int32_t precond;          /* MLB_PRECOND_NONE, MLB_PRECOND_JACOBI or MLB_PRECOND_ILU0 */
   int32_t transpose_free;   /* 0: Algorithm 7.1 with A^H; 1: without A^H       */
   int32_t order;            /* MLB_ORDER_FUSED (0) or MLB_ORDER_LITERAL (1)    */
 } mlb_options;

@@ -18,7 +18,7 @@ MLB_EINVAL, MLB_ENOMEM, MLB_EHIP, MLB_EUNSUPPORTED = -2, -3, -4, -5
 MLB_R64, MLB_C128 = 0, 1
 MLB_CSR, MLB_BSR3 = 0, 1
 MLB_PREC_FP64, MLB_PREC_FP32_IR = 0, 1
-MLB_PRECOND_NONE, MLB_PRECOND_JACOBI = 0, 1
+MLB_PRECOND_NONE, MLB_PRECOND_JACOBI, MLB_PRECOND_ILU0 = 0, 1, 2
 MLB_ORDER_FUSED, MLB_ORDER_LITERAL = 0, 1
 MLB_OP_A, MLB_OP_AH = 0, 1
 MLB_MAX_N = 32

@@ -35,6 +35,7 @@
 #include "mlb_spmv.hpp"
 #include "mlb_small.hpp"
 #include "mlb_precond.hpp"
+#include "mlb_ilu.hpp"
 #include "mlb_transpose.hpp"
 
 namespace mlb {
@@ -203,6 +204,193 @@ static Mat<V> build_transpose(const Mat<V>& A, Allocs& al, hipStream_t s) {
   return T;
 }
 
+// ------------------------------------------------------------------ ILU(0)
+
+// Level sets of the dependencies of a row-sorted pattern: lower = rows j < i of
+// row i (forward substitution), else rows j > i (backward).  The row order is
+// grouped by level (rows in increasing order inside a level); ptr[l] .. ptr[l+1]
+// are the rows of level l.  Integer set-up work on the host over a copy of the
+// index arrays.
+static void level_sets(const std::vector<int>& rp, const std::vector<int>& ci, bool lower, std::vector<int>& order,
+                       std::vector<int>& ptr) {
+  const int m = (int)rp.size() - 1;
+  std::vector<int> lev((size_t)m, 0);
+  int nlev = 0;
+  for (int t = 0; t < m; ++t) {
+    const int i = lower ? t : m - 1 - t;
+    int l = 0;
+    for (int q = rp[i]; q < rp[i + 1]; ++q) {
+      const int j = ci[q];
+      if (lower ? j < i : j > i) l = std::max(l, lev[j] + 1);
+    }
+    lev[i] = l;
+    nlev = std::max(nlev, l + 1);
+  }
+  ptr.assign((size_t)nlev + 1, 0);
+  for (int i = 0; i < m; ++i) ptr[lev[i] + 1]++;
+  for (int l = 0; l < nlev; ++l) ptr[l + 1] += ptr[l];
+  order.assign((size_t)m, 0);
+  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  for (int i = 0; i < m; ++i) order[fill[lev[i]]++] = i;
+}
+
+// The ILU(0) factor of A, its conjugate transpose and the level sets of the
+// four triangular solves (L, U of the factor; U^H, L^H of its transpose).
+template <class V>
+struct IluFactor {
+  int bs = 1, nbrows = 0;
+  Mat<V> F, FH;                       // factor (A's sorted pattern) and its conjugate transpose
+  int* dpos = nullptr;                // diagonal positions in F and FH
+  int* dposH = nullptr;
+  V* dinv = nullptr;                  // inverse diagonal (blocks) of F (U_ii^{-1}) and FH ((U_ii^H)^{-1})
+  V* dinvH = nullptr;
+  int *ordL = nullptr, *ordU = nullptr, *ordHf = nullptr, *ordHb = nullptr;   // rows by level (device)
+  std::vector<int> ptrL, ptrU, ptrHf, ptrHb;                                   // level pointers (host)
+  V* tmid = nullptr;                  // intermediate vector of the two solves
+};
+
+static int level_grid(int count) { return std::max(1, std::min((count + BLOCK - 1) / BLOCK, 4096)); }
+
+template <class V, int BS, bool LOWER, bool UNIT>
+static void ilu_sweep(const Mat<V>& M, const int* dpos, const V* dinv, const int* ord, const std::vector<int>& ptr,
+                      const V* in, V* out, hipStream_t s, const int* done) {
+  const int nlev = (int)ptr.size() - 1;
+  for (int t = 0; t < nlev; ++t) {
+    const int c = ptr[t + 1] - ptr[t];   // levels in the order they are solved
+    k_ilu_solve_level<V, BS, LOWER, UNIT><<<level_grid(c), BLOCK, 0, s>>>(M.rp, M.ci, M.val, dpos, dinv,
+                                                                          ord + ptr[t], c, in, out, done);
+  }
+}
+
+// out = M^{-1} in = U^{-1} (L^{-1} in) (in, out distinct from f.tmid and from each other).
+template <class V>
+static void ilu_apply(const IluFactor<V>& f, const V* in, V* out, hipStream_t s, const int* done) {
+  if (f.bs == 1) {
+    ilu_sweep<V, 1, true, true>(f.F, f.dpos, f.dinv, f.ordL, f.ptrL, in, f.tmid, s, done);
+    ilu_sweep<V, 1, false, false>(f.F, f.dpos, f.dinv, f.ordU, f.ptrU, f.tmid, out, s, done);
+  } else {
+    ilu_sweep<V, 3, true, true>(f.F, f.dpos, f.dinv, f.ordL, f.ptrL, in, f.tmid, s, done);
+    ilu_sweep<V, 3, false, false>(f.F, f.dpos, f.dinv, f.ordU, f.ptrU, f.tmid, out, s, done);
+  }
+}
+
+// v = M^{-H} v = L^{-H} (U^{-H} v), in place through f.tmid.
+template <class V>
+static void ilu_apply_h(const IluFactor<V>& f, V* v, hipStream_t s, const int* done) {
+  if (f.bs == 1) {
+    ilu_sweep<V, 1, true, false>(f.FH, f.dposH, f.dinvH, f.ordHf, f.ptrHf, v, f.tmid, s, done);
+    ilu_sweep<V, 1, false, true>(f.FH, f.dposH, f.dinvH, f.ordHb, f.ptrHb, f.tmid, v, s, done);
+  } else {
+    ilu_sweep<V, 3, true, false>(f.FH, f.dposH, f.dinvH, f.ordHf, f.ptrHf, v, f.tmid, s, done);
+    ilu_sweep<V, 3, false, true>(f.FH, f.dposH, f.dinvH, f.ordHb, f.ptrHb, f.tmid, v, s, done);
+  }
+}
+
+// x <- M x = L (U x) in place through f.tmid (the map y_0 = M x_0).
+template <class V>
+static void ilu_forward_map(const IluFactor<V>& f, V* x, hipStream_t s) {
+  const int g = grid_for(f.nbrows, 4096);
+  if (f.bs == 1) {
+    k_ilu_tri_matvec<V, 1, false><<<g, BLOCK, 0, s>>>(f.F.rp, f.F.ci, f.F.val, f.dpos, f.nbrows, x, f.tmid);
+    k_ilu_tri_matvec<V, 1, true><<<g, BLOCK, 0, s>>>(f.F.rp, f.F.ci, f.F.val, f.dpos, f.nbrows, f.tmid, x);
+  } else {
+    k_ilu_tri_matvec<V, 3, false><<<g, BLOCK, 0, s>>>(f.F.rp, f.F.ci, f.F.val, f.dpos, f.nbrows, x, f.tmid);
+    k_ilu_tri_matvec<V, 3, true><<<g, BLOCK, 0, s>>>(f.F.rp, f.F.ci, f.F.val, f.dpos, f.nbrows, f.tmid, x);
+  }
+}
+
+static std::vector<int> to_host(const int* d, size_t count, hipStream_t s) {
+  std::vector<int> h(count);
+  if (count) HIP_TRY(hipMemcpyAsync(h.data(), d, count * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return h;
+}
+
+// Builds the ILU(0) factor of A on the device: a row-sorted copy of A, the
+// pattern checks, the level sets, the factorisation level by level, the
+// conjugate transpose with its diagonal inverses.  Throws MLB_EINVAL for a
+// missing diagonal, a repeated column in a row or a zero / singular pivot.
+template <class V>
+static void build_ilu(const Mat<V>& A, IluFactor<V>& f, Allocs& al, hipStream_t s) {
+  const int m = A.nbrows;
+  const int bs = A.format == MLB_BSR3 ? 3 : 1;
+  const int b2 = bs * bs;
+  f.bs = bs;
+  f.nbrows = m;
+  f.F = A;
+  int* ci = al.get<int>((size_t)A.nnz);
+  V* val = al.get<V>((size_t)A.nnz * b2);
+  if (A.nnz > 0) {
+    HIP_TRY(hipMemcpyAsync(ci, A.ci, sizeof(int) * A.nnz, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(val, A.val, sizeof(V) * A.nnz * b2, hipMemcpyDeviceToDevice, s));
+  }
+  if (bs == 1) k_sort_rows<V, 1><<<grid_for(m, 4096), BLOCK, 0, s>>>(A.rp, m, ci, val);
+  else k_sort_rows<V, 9><<<grid_for(m, 4096), BLOCK, 0, s>>>(A.rp, m, ci, val);
+  f.F.ci = ci;
+  f.F.val = val;
+  f.dpos = al.get<int>(m);
+  f.dinv = al.get<V>((size_t)m * b2);
+  f.tmid = al.get<V>((size_t)m * bs);
+  Allocs tmp_own(al.stream, al.ordered);
+  int* bad = tmp_own.get<int>(1);
+  k_fill<int><<<1, BLOCK, 0, s>>>(bad, 1, 0);
+  k_ilu_diag_pos<<<grid_for(m, 4096), BLOCK, 0, s>>>(A.rp, ci, m, f.dpos, bad);
+  HIP_TRY(hipGetLastError());
+  int hb = 0;
+  HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hb & 1) throw Error{MLB_EINVAL, "ILU(0): a (block) row has no stored diagonal entry"};
+  if (hb & 4) throw Error{MLB_EINVAL, "ILU(0): a column is stored twice in one (block) row"};
+  // level sets of the factor's solves (and of the factorisation, the same as L's)
+  const std::vector<int> hrp = to_host(A.rp, (size_t)m + 1, s);
+  const std::vector<int> hci = to_host(ci, (size_t)A.nnz, s);
+  std::vector<int> ord;
+  level_sets(hrp, hci, true, ord, f.ptrL);
+  f.ordL = al.get<int>(m);
+  HIP_TRY(hipMemcpyAsync(f.ordL, ord.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  std::vector<int> ordU;
+  level_sets(hrp, hci, false, ordU, f.ptrU);
+  f.ordU = al.get<int>(m);
+  HIP_TRY(hipMemcpyAsync(f.ordU, ordU.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  // factorisation, one launch per level of L
+  for (size_t l = 0; l + 1 < f.ptrL.size(); ++l) {
+    const int c = f.ptrL[l + 1] - f.ptrL[l];
+    if (bs == 1)
+      k_ilu_factor_level<V, 1><<<level_grid(c), BLOCK, 0, s>>>(A.rp, ci, val, f.dpos, f.dinv, f.ordL + f.ptrL[l], c, bad);
+    else
+      k_ilu_factor_level<V, 3><<<level_grid(c), BLOCK, 0, s>>>(A.rp, ci, val, f.dpos, f.dinv, f.ordL + f.ptrL[l], c, bad);
+  }
+  HIP_TRY(hipGetLastError());
+  // conjugate transpose of the factor (rows sorted) and its diagonal inverses
+  f.FH = build_transpose(f.F, al, s);
+  f.dposH = al.get<int>(m);
+  f.dinvH = al.get<V>((size_t)m * b2);
+  k_ilu_diag_pos<<<grid_for(m, 4096), BLOCK, 0, s>>>(f.FH.rp, f.FH.ci, m, f.dposH, bad);
+  if (bs == 1) k_ilu_inv_diag<V, 1><<<grid_for(m, 4096), BLOCK, 0, s>>>(f.FH.val, f.dposH, m, f.dinvH, bad);
+  else k_ilu_inv_diag<V, 3><<<grid_for(m, 4096), BLOCK, 0, s>>>(f.FH.val, f.dposH, m, f.dinvH, bad);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hb & 2) throw Error{MLB_EINVAL, "ILU(0): a zero or singular pivot"};
+  const std::vector<int> hrpH = to_host(f.FH.rp, (size_t)m + 1, s);
+  const std::vector<int> hciH = to_host(f.FH.ci, (size_t)A.nnz, s);
+  std::vector<int> ordHf, ordHb;
+  level_sets(hrpH, hciH, true, ordHf, f.ptrHf);
+  level_sets(hrpH, hciH, false, ordHb, f.ptrHb);
+  f.ordHf = al.get<int>(m);
+  f.ordHb = al.get<int>(m);
+  HIP_TRY(hipMemcpyAsync(f.ordHf, ordHf.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(f.ordHb, ordHb.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));   // the host vectors above are copied before they go
+}
+
+// Device bytes build_ilu allocates (beside the transpose's own temporaries).
+static size_t ilu_bytes(long long nnz, int m, int bs, size_t sv) {
+  const size_t b2 = (size_t)bs * bs;
+  return (size_t)nnz * 4 * 2 + (size_t)nnz * b2 * sv * 2 + (size_t)(m + 1) * 4 + (size_t)m * 4 * 6 +
+         (size_t)m * b2 * sv * 2 + (size_t)m * bs * sv;
+}
+
 // ------------------------------------------------------------------ launch dispatch
 
 // Kernel timing hook: a pair of HIP events attached to one launch.  With
@@ -325,6 +513,10 @@ struct Engine {
   bool poll = false;
   static constexpr int POLL_CYCLES = 4;
   bool tf = false;   // transpose-free inner steps: no A^H, no F (set before init)
+  // ILU(0) from the right (set before init): every product with A is preceded by
+  // M^{-1} applied to its input (into tpre), and f_s = M^{-H} (A^H q_s).
+  const IluFactor<V>* ilu = nullptr;
+  V* tpre = nullptr;
   bool literal = false;   // beta~ and beta recurrences in the sequential order, one reduction per coefficient
 
   // ext_flag: a pinned, host-mapped int the caller owns (serving workers reuse one
@@ -343,6 +535,7 @@ struct Engine {
     r = al.get<V>(N);
     gt = al.get<V>(N);
     z = al.get<V>(N);
+    if (ilu) tpre = al.get<V>(N);
     st = al.get<State<Sc>>(1);
     part = al.get<Sc>((size_t)MAX_PARTIAL_ROWS * (NMAX + 1));
     part2 = al.get<Sc>((size_t)PSUM_GRID * (NMAX + 1));
@@ -463,20 +656,26 @@ struct Engine {
   void spmv_resid(const Mat<V>& M, const V* xin, const V* b, V* out, const V* Qc, int phase, int flags = 0) {
     SpmvArgs<V> a{};
     a.format = M.format; a.nrows = M.nrows; a.nbrows = M.nbrows; a.rp = M.rp; a.ci = M.ci; a.val = M.val;
-    a.xin = xin; a.out1 = out; a.b = b; a.Q = Qc; a.nd = Qc ? 1 : 0;
+    a.xin = xin; a.xown = xin; a.out1 = out; a.b = b; a.Q = Qc; a.nd = Qc ? 1 : 0;
     launch_spmv_nd<V, Sc, SM_RESID, 4>(M, grid_spmv, s, st, part, a, phase, 0, 0, n, flags);
     if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, 4, 3, phase, 0, 0);
   }
   void spmv_plain(const Mat<V>& M, const V* xin, V* out, int flags = 0) {
     SpmvArgs<V> a{};
     a.format = M.format; a.nrows = M.nrows; a.nbrows = M.nbrows; a.rp = M.rp; a.ci = M.ci; a.val = M.val;
-    a.xin = xin; a.out1 = out;
+    a.xin = xin; a.xown = xin; a.out1 = out;
     launch_spmv_nd<V, Sc, SM_PLAIN, 4>(M, grid_spmv, s, st, part, a, PH_NONE, 0, 0, n, flags);
+  }
+  // The vector a product with A M^{-1} multiplies: v itself, or M^{-1} v in tpre.
+  const V* pre(const V* v) {
+    if (!ilu) return v;
+    ilu_apply(*ilu, v, tpre, s, (force_flags & F_IGNORE_DONE) ? nullptr : &st->done);
+    return tpre;
   }
   void spmv_omega(const V* u, V* zout) {
     SpmvArgs<V> a{};
     a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
-    a.xin = u; a.out1 = zout;
+    a.xin = pre(u); a.xown = u; a.out1 = zout;
     launch_spmv_nd<V, Sc, SM_OMEGA, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_OMEGA, 0, 0, n, force_flags);
     scalar(grid_spmv, 4, 2, PH_SPMV_OMEGA, 0, 0);
   }
@@ -491,7 +690,7 @@ struct Engine {
   void spmv_h(const V* gin, int i, int j) {
     SpmvArgs<V> a{};
     a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
-    a.xin = gin; a.out1 = W + (size_t)i * N; a.out2 = nullptr;
+    a.xin = pre(gin); a.xown = gin; a.out1 = W + (size_t)i * N; a.out2 = nullptr;
     a.Q = Q; a.ldq = ldq; a.d0 = 0; a.nd = i;
     const int flags = force_flags;
     const Timed tm = timed(MLB_KERNEL_SPMV_STEP);
@@ -526,7 +725,7 @@ struct Engine {
     SpmvArgs<V> a{};
     a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
     V* Gi = G + (size_t)i * N;
-    a.xin = gin; a.out1 = W + (size_t)i * N; a.out2 = gin == Gi ? nullptr : Gi;
+    a.xin = pre(gin); a.xown = gin; a.out1 = W + (size_t)i * N; a.out2 = gin == Gi ? nullptr : Gi;
     a.Q = Q; a.ldq = ldq; a.d0 = i; a.nd = literal ? 1 : n - i;
     flags |= force_flags;
     const Timed tm = timed(MLB_KERNEL_SPMV_STEP);
@@ -691,10 +890,13 @@ struct Engine {
     HIP_TRY(hipEventRecord(t0, s));
     k_init_state<Sc><<<1, 1, 0, s>>>(st, tol, maxit, kappa, host_done_dev, stag_window);
     // r_0 = b - A x_0, ||b||, e_0 = q_1^H r_0, early exit
-    spmv_resid(A, x, b, r, Q, PH_SETUP);
-    // f_s = A^H q_s, s = 1..n-1 (not used by the transpose-free steps)
+    spmv_resid(A, pre(x), b, r, Q, PH_SETUP);
+    // f_s = M^{-H} A^H q_s, s = 1..n-1 (not used by the transpose-free steps)
     if (!tf)
-      for (int c = 0; c + 1 < n; ++c) spmv_plain(AH, Q + (size_t)c * ldq, F + (size_t)c * N);
+      for (int c = 0; c + 1 < n; ++c) {
+        spmv_plain(AH, Q + (size_t)c * ldq, F + (size_t)c * N);
+        if (ilu) ilu_apply_h(*ilu, F + (size_t)c * N, s, &st->done);
+      }
     // g_0 = r_0, w_0 = A g_0, c_0 (and S column 0), alpha_1 = e_0 / c_0
     spmv_step(r, 0);
     HIP_TRY(hipEventRecord(t1, s));
@@ -730,9 +932,12 @@ struct Engine {
     Q = Q_;
     ldq = ldq_;
     k_init_state<Sc><<<1, 1, 0, s>>>(st, tol, maxit, kappa, nullptr, stag_window);
-    spmv_resid(A, x, b, r, Q, PH_SETUP);
+    spmv_resid(A, pre(x), b, r, Q, PH_SETUP);
     if (!tf)
-      for (int c = 0; c + 1 < n; ++c) spmv_plain(AH, Q + (size_t)c * ldq, F + (size_t)c * N);
+      for (int c = 0; c + 1 < n; ++c) {
+        spmv_plain(AH, Q + (size_t)c * ldq, F + (size_t)c * N);
+        if (ilu) ilu_apply_h(*ilu, F + (size_t)c * N, s, &st->done);
+      }
     spmv_step(r, 0);
     HIP_TRY(hipGetLastError());
     const long long max_cycles = maxit / n + 2;
@@ -787,6 +992,8 @@ struct Impl {
   int bs = 1;           // 1 (CSR) or 3 (BSR3): size of the diagonal blocks of M
   V64* Mblk = nullptr;  // diagonal (blocks) of A, when preconditioned
   V64* Minv = nullptr;  // their inverses
+  IluFactor<V64> ilu;   // ILU(0) factor, when has_ilu
+  bool has_ilu = false;
   void release() {
     e64.release();
     if (has32) e32.release();
@@ -828,8 +1035,10 @@ static void check_options(const mlb_options* opt) {
   if (!(opt->kappa >= 0.0) || !std::isfinite(opt->kappa)) throw Error{MLB_EINVAL, "kappa must be finite and >= 0"};
   if (opt->precision != MLB_PREC_FP64 && opt->precision != MLB_PREC_FP32_IR)
     throw Error{MLB_EINVAL, "precision must be MLB_PREC_FP64 or MLB_PREC_FP32_IR"};
-  if (opt->precond != MLB_PRECOND_NONE && opt->precond != MLB_PRECOND_JACOBI)
-    throw Error{MLB_EINVAL, "precond must be MLB_PRECOND_NONE or MLB_PRECOND_JACOBI"};
+  if (opt->precond != MLB_PRECOND_NONE && opt->precond != MLB_PRECOND_JACOBI && opt->precond != MLB_PRECOND_ILU0)
+    throw Error{MLB_EINVAL, "precond must be MLB_PRECOND_NONE, MLB_PRECOND_JACOBI or MLB_PRECOND_ILU0"};
+  if (opt->precond == MLB_PRECOND_ILU0 && opt->precision != MLB_PREC_FP64)
+    throw Error{MLB_EUNSUPPORTED, "ILU(0) runs with the fp64 iteration only"};
   if (opt->transpose_free != 0 && opt->transpose_free != 1) throw Error{MLB_EINVAL, "transpose_free must be 0 or 1"};
   if (opt->order != MLB_ORDER_FUSED && opt->order != MLB_ORDER_LITERAL)
     throw Error{MLB_EINVAL, "order must be MLB_ORDER_FUSED or MLB_ORDER_LITERAL"};
@@ -910,6 +1119,12 @@ static void create_impl(mlb_solver* h, const mlb_matrix* Adesc, Impl<V64, V32>& 
     if (hb & 1) throw Error{MLB_EINVAL, "Jacobi preconditioner: a (block) row has no stored diagonal entry"};
     if (hb & 2) throw Error{MLB_EINVAL, "Jacobi preconditioner: a diagonal (block) is singular"};
     A.val = scaled;
+  }
+  if (h->opt.precond == MLB_PRECOND_ILU0) {
+    // M = ILU(0) of A; the iteration multiplies by A after M^{-1}
+    build_ilu(A, im.ilu, h->al, h->s);
+    im.has_ilu = true;
+    im.e64.ilu = &im.ilu;
   }
   const bool tf = h->opt.transpose_free != 0;
   const Mat<V64> AH = tf ? Mat<V64>{} : build_transpose(A, h->al, h->s);
@@ -998,6 +1213,14 @@ static bool debug_enabled() {
 // x <- M x (forward) or x <- M^{-1} x (back) for `cols` columns; no-op without a preconditioner.
 template <class V64, class V32>
 static void precond_map(mlb_solver* h, Impl<V64, V32>& im, V64* x, int cols, long long ld, bool back) {
+  if (im.has_ilu) {
+    for (int c = 0; c < cols; ++c) {
+      V64* xc = x + (size_t)c * ld;
+      if (back) ilu_apply(im.ilu, xc, xc, h->s, nullptr);
+      else ilu_forward_map(im.ilu, xc, h->s);
+    }
+    return;
+  }
   if (!im.Minv || cols <= 0) return;
   const V64* blk = back ? im.Minv : im.Mblk;
   const int nbr = im.A0.nbrows;
@@ -1415,6 +1638,8 @@ int mlbicgstab_workspace_size(const mlb_matrix* A, const mlb_options* opt, size_
     t += (size_t)N * sv;                                                                   // r64
     if (opt->precond == MLB_PRECOND_JACOBI)                                                // M, M^{-1}, A M^{-1}
       t += (size_t)nbr * bs * 2 * sv + (size_t)A->nnz * bs * sv;
+    if (opt->precond == MLB_PRECOND_ILU0)                                                  // factor, its transpose, M^{-1} v
+      t += ilu_bytes(A->nnz, nbr, A->format == MLB_BSR3 ? 3 : 1, sv) + (size_t)N * sv;
     if (opt->precision == MLB_PREC_FP32_IR) {
       t += (size_t)A->nnz * bs * (tf ? sv / 2 : sv);                                       // fp32 A (and A^H) values
       t += c ? Engine<cplx<float>>::bytes(N, opt->n, tf) : Engine<float>::bytes(N, opt->n, tf);

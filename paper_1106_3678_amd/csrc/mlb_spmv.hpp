@@ -166,8 +166,8 @@ __device__ inline void bsr3_tile(const int* __restrict__ rp, const int* __restri
 enum SpmvMode : int {
   SM_PLAIN = 0,   // out1 = A x
   SM_RESID = 1,   // out1 = b - A x ; sums: ||out1||^2, ||b||^2, q_1^H out1
-  SM_STEP = 2,    // out1 = A x ; out2 = x (if given) ; sums: q_s^H out1, s in [d0, d0+nd)
-  SM_OMEGA = 3    // out1 = A x ; sums: out1^H out1, out1^H x
+  SM_STEP = 2,    // out1 = A x ; out2 = xown (if given) ; sums: q_s^H out1, s in [d0, d0+nd)
+  SM_OMEGA = 3    // out1 = A x ; sums: out1^H out1, out1^H xown
 };
 
 template <class V>
@@ -178,7 +178,9 @@ struct SpmvArgs {
   const int* rp;
   const int* ci;
   const V* val;
-  const V* xin;
+  const V* xin;               // the vector multiplied (gathered)
+  const V* xown;              // the vector the epilogue reads row by row: xin, or with a
+                              // preconditioner the vector xin = M^{-1} xown was made from
   V* out1;
   V* out2;
   const V* b;                 // SM_RESID
@@ -218,14 +220,14 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(State<Sc>* st, Sc* partial, Spmv
         if (a.nd > 0) cdot_acc(acc[2], a.Q[row], rv);
       } else if constexpr (MODE == SM_STEP) {
         a.out1[row] = y;
-        if (a.out2) a.out2[row] = a.xin[row];
+        if (a.out2) a.out2[row] = a.xown[row];
 #pragma unroll
         for (int d = 0; d < ND; ++d)
           if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
       } else {  // SM_OMEGA
         a.out1[row] = y;
         cdot_acc(acc[0], y, y);
-        cdot_acc(acc[1], y, a.xin[row]);
+        cdot_acc(acc[1], y, a.xown[row]);
       }
     }
     __syncthreads();
@@ -323,14 +325,14 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_bsrw(State<Sc>* st, Sc* partial,
         if (a.nd > 0) cdot_acc(acc[2], a.Q[row], rv);
       } else if constexpr (MODE == SM_STEP) {
         a.out1[row] = y;
-        if (a.out2) a.out2[row] = a.xin[row];
+        if (a.out2) a.out2[row] = a.xown[row];
 #pragma unroll
         for (int d = 0; d < ND; ++d)
           if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
       } else {  // SM_OMEGA
         a.out1[row] = y;
         cdot_acc(acc[0], y, y);
-        cdot_acc(acc[1], y, a.xin[row]);
+        cdot_acc(acc[1], y, a.xown[row]);
       }
     }
   }
@@ -432,14 +434,14 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csrw(State<Sc>* st, Sc* partial,
         if (a.nd > 0) cdot_acc(acc[2], a.Q[row], rv);
       } else if constexpr (MODE == SM_STEP) {
         a.out1[row] = y;
-        if (a.out2) a.out2[row] = a.xin[row];
+        if (a.out2) a.out2[row] = a.xown[row];
 #pragma unroll
         for (int d = 0; d < ND; ++d)
           if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
       } else {  // SM_OMEGA
         a.out1[row] = y;
         cdot_acc(acc[0], y, y);
-        cdot_acc(acc[1], y, a.xin[row]);
+        cdot_acc(acc[1], y, a.xown[row]);
       }
     }
   }

@@ -1,0 +1,137 @@
+"""ILU(0) right preconditioning (the paper's preconditioner, Section 5) on the GPU against the oracle
+preconditioned with oracle.ilu0 (point ILU(0) for CSR, 3x3-block ILU(0) for BSR3).
+
+Same bars as the other parity tests: flag, iteration count within 5%, x_1..x_20 within 1e-8, true
+residual below tol, x within 1e-6 -- strict everywhere except the ill-conditioned reservoir system,
+whose early iterates the oracle itself moves by up to 120% under a 1e-15 perturbation of b (there
+only the flag, the count, the residual and the final x are compared).  Also: a nonzero x_0 (the map y_0 = M x_0), the transpose-free and literal orders,
+the 128^3 benchmark operator with n = 4 against the oracle run to convergence, and the errors.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads
+from oracle.ilu0 import ilu0_precond
+from tests.gpu_util import check_against_bars, gpu_available, parity_bars, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import torch  # noqa: E402
+
+from paper_1106_3678_amd import binding  # noqa: E402
+
+ILU = binding.MLB_PRECOND_ILU0
+
+
+def run_oracle_ilu(p, K=20, transpose_free=False, pre=None):
+    return oracle.mlbicgstabt(p.A, p.b, p.Q, x0=p.x0, tol=p.tol, maxit=p.maxit, kappa=p.kappa, record_x=K,
+                              precond=pre or ilu0_precond(p.A), transpose_free=transpose_free)
+
+
+def check_ilu(p, K=20, mode="strict", transpose_free=False, order=0, iterates_cap=1e-6):
+    res, x, its = run_gpu(p, record=K, precond=ILU, transpose_free=transpose_free, order=order)
+    pre = ilu0_precond(p.A)
+    o = run_oracle_ilu(p, K, transpose_free, pre)
+    b = parity_bars(p, o, K, mode, precond=pre, transpose_free=transpose_free, n_perturb=6,
+                    iterates_cap=iterates_cap)
+    check_against_bars(" (ILU(0))", p, res, x, its, o, b, K)
+    return res, x, o
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8])
+def test_convdiff2d_32(n):
+    check_ilu(workloads.config1(n=n))
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_convdiff2d_ragged(n):
+    check_ilu(workloads.config1(n=n, m=33))
+
+
+@pytest.mark.parametrize("n", [1, 4, 16])
+def test_convdiff3d(n):
+    check_ilu(workloads.config2(n=n, m=20, maxit=4000))
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_complex(n):
+    check_ilu(workloads.config5(n=n, m=12, maxit=4000))
+
+
+@pytest.mark.parametrize("grid,n", [((8, 10, 6), 4), ((12, 16, 6), 8), ((9, 14, 7), 4)])
+def test_bsr3_block_ilu_well_conditioned(grid, n):
+    """Reservoir-shaped systems with the larger diagonal term: block ILU(0), strict bars."""
+    check_ilu(workloads.config3(n=n, grid=grid, maxit=4000, accum=1.0))
+
+
+def test_bsr3_block_ilu_benchmark_conditioning():
+    """The benchmark's conditioning (12x16x6, n = 8): the oracle's count does not move under rounding
+    here; strict bars."""
+    check_ilu(workloads.config3(n=8, grid=(12, 16, 6), maxit=4000))
+
+
+def test_bsr3_block_ilu_chaotic():
+    """8x10x6 at the benchmark's conditioning: rounding alone moves the oracle's own x_1..x_20 by up to
+    120% (a near-breakdown early in the iteration), so the iterates bound nothing here; the flag, the
+    count (within 15% of the oracle's range), the true residual and the final x (1e-6) are checked."""
+    check_ilu(workloads.config3(n=4, grid=(8, 10, 6), maxit=4000), mode="chaotic", iterates_cap=None)
+
+
+def test_nonzero_initial_guess():
+    p = workloads.config2(n=4, m=16, maxit=4000)
+    p.x0 = np.random.default_rng(3).standard_normal(p.N)
+    check_ilu(p)
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_transpose_free(n):
+    check_ilu(workloads.config2(n=n, m=16, maxit=4000), transpose_free=True)
+
+
+def test_literal_order():
+    check_ilu(workloads.config2(n=4, m=16, maxit=4000), order=binding.MLB_ORDER_LITERAL)
+
+
+def test_kappa_guard():
+    p = workloads.config1(n=4)
+    p.kappa = 0.7
+    check_ilu(p)
+
+
+def test_full_size_convdiff3d_n4():
+    """The 128^3 benchmark operator (N = 2,097,152) with ILU(0), n = 4, in the benchmark's launch
+    configuration, against the oracle run to convergence."""
+    p = workloads.config2(n=4, m=128)
+    check_ilu(p)
+
+
+def _solver_error(A, opt_precond=ILU, precision=0):
+    p = workloads.Problem("e", A, np.ones(A.shape[0]), np.ones((A.shape[0], 1)), np.zeros(A.shape[0]), 1,
+                          1e-10, 10)
+    with pytest.raises(binding.MlbError) as e:
+        run_gpu(p, precond=opt_precond, precision=precision)
+    return e.value
+
+
+def test_errors():
+    # no stored diagonal in row 1
+    A = sp.csr_matrix(np.array([[2.0, 1.0, 0.0], [1.0, 0.0, 1.0], [0.0, 1.0, 2.0]]))
+    A.eliminate_zeros()
+    err = _solver_error(A)
+    assert err.code == binding.MLB_EINVAL and "diagonal" in str(err)
+    # a zero pivot: u_11 = 1 - 1 = 0
+    A = sp.csr_matrix(np.array([[1.0, 1.0], [1.0, 1.0]]))
+    err = _solver_error(A)
+    assert err.code == binding.MLB_EINVAL and "pivot" in str(err)
+    # a column stored twice in one row
+    A = sp.csr_matrix((np.array([2.0, 1.0, 1.0, 2.0]), np.array([0, 1, 1, 1]), np.array([0, 1, 4])), shape=(2, 2))
+    err = _solver_error(A)
+    assert err.code == binding.MLB_EINVAL and "twice" in str(err)
+    # fp32 refinement is not combined with ILU(0)
+    err = _solver_error(sp.identity(4, format="csr"), precision=binding.MLB_PREC_FP32_IR)
+    assert err.code == binding.MLB_EUNSUPPORTED
