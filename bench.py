@@ -474,6 +474,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="number of shadow vectors (0 = the workload's)")
     ap.add_argument("--m", type=int, default=0, help="grid points per dimension (0 = the workload's)")
     ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--velocity", default="constant", choices=["constant", "smooth"],
+                    help="convdiff3d: one seeded direction (the benchmark's), or a smooth random direction field")
     ap.add_argument("--order", default="fused", choices=["fused", "literal"],
                     help="recurrence order: Gram-matrix form (fused) or the sequential loops (literal)")
     ap.add_argument("--transpose-free", action="store_true",
@@ -513,7 +515,7 @@ def main():
         print(json.dumps(bench_serving_sequences(args, torch, workloads, binding)), flush=True)
         return
     t = time.perf_counter()
-    p, fmt, cplx, grid = make_problem(args.workload, workloads, args.n, args.m)
+    p, fmt, cplx, grid = make_problem(args.workload, workloads, args.n, args.m, args.velocity)
     nnz = int(p.A.indptr[-1])          # entries (CSR) or 3x3 blocks (BSR3)
     profile_key = {"convdiff3d": f"convdiff3d_m{args.m or 128}_n{p.n}", "reservoir": f"reservoir_n{p.n}",
                    "helmholtz": f"helmholtz_m{args.m or 96}_n{p.n}"}[args.workload]
@@ -627,10 +629,10 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def make_problem(workload, workloads, n=0, m=0):
+def make_problem(workload, workloads, n=0, m=0, velocity="constant"):
     """(problem, storage, complex?, grid) of a solve workload."""
     if workload == "convdiff3d":
-        return workloads.config2(n=n or 4, m=m or 128), "csr", False, [m or 128] * 3
+        return workloads.config2(n=n or 4, m=m or 128, velocity=velocity), "csr", False, [m or 128] * 3
     if workload == "reservoir":
         p = workloads.config3(n=n or 8)
         return p, "bsr3", False, list(p.meta["grid"])

@@ -107,3 +107,23 @@ def test_full_size_reservoir_fp32_refinement():
     assert abs(true - res.err_true) < 1e-12
     assert true <= 1e-10
     assert np.isfinite(x).all()
+
+
+@pytest.mark.parametrize("case", ["smooth_field_64", "reservoir_no_preconditioner"])
+def test_plain_variants_stall(case):
+    """The two workloads the benchmark eases (one seeded velocity direction instead of a smooth random
+    field; block Jacobi on the reservoir system): their plain forms match the oracle's first iterates,
+    then do not reach the target accuracy: within the iterations given, either no convergence, or a
+    recursive residual below tol whose true residual stays far above 1e-10 (the excursions of the
+    residual, thousands of times ||b|| on the smooth field, leave a large recursive/true gap)."""
+    if case == "smooth_field_64":
+        p = workloads.config2(n=4, m=64, velocity="smooth", maxit=4000)
+        res, x, its = run_gpu(p, record=20)
+    else:
+        p = workloads.config3(n=8, maxit=2000)
+        res, x, its = run_gpu(p, record=20)
+    first_iterates(p, res, its)
+    print(f"  plain {case}: flag {res.flag} iter {res.iter} recursive {res.err_recursive:.2e} "
+          f"true {res.err_true:.2e}", flush=True)
+    assert not (res.flag == 0 and res.err_true <= 1e-10)
+    assert res.err_true > 1e-8
