@@ -459,6 +459,8 @@ def main():
     ap.add_argument("--workload", default="convdiff3d",
                     choices=["convdiff3d", "reservoir", "helmholtz", "serving", "sequence", "serving-seq"])
     ap.add_argument("--matrices", type=int, default=200, help="serving-seq: matrices (sequences)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="serving: skip the same requests as sequential fp64 solves")
     ap.add_argument("--seq-nmin", type=float, default=1e3, help="serving-seq: smallest target N of the matrices")
     ap.add_argument("--systems", type=int, default=10, help="sequence: right-hand sides")
     ap.add_argument("--seq-matrix", default="convdiff3d", choices=["convdiff3d", "reservoir"],
@@ -506,7 +508,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     if args.workload == "serving":
-        print(json.dumps(bench_serving(args, torch, workloads, binding)), flush=True)
+        print(json.dumps(bench_serving(args, torch, workloads, binding, sequential=not args.no_sequential)),
+              flush=True)
         return
     if args.workload == "sequence":
         print(json.dumps(bench_sequence(args, torch, workloads, binding)), flush=True)
