@@ -32,19 +32,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False, literal=False):
-    """Algorithmic bytes of one SpMV-step launch (w_i = A g_i with q_s^H w_i, s = i..n-1),
-    averaged over the launches i = 0..n-1 of one cycle.
+def s_from_alpha(n, transpose_free=False, literal=False, sv=8):
+    """Whether the library takes the S column of w_i below its diagonal (q_s^H w_i, s > i) from the next
+    alpha pass, so that the SpMV step reduces only c_i = q_i^H w_i: the Gram-form steps with A^H whose
+    bucket of n (4, 8, 16, 32) is 8 or 16 with 2 nb + 1 accumulators of sv bytes within 288 bytes (real
+    n in 5..16, complex n in 5..8)."""
+    nb = 4 if n <= 4 else 8 if n <= 8 else 16 if n <= 16 else 32
+    return not transpose_free and not literal and 8 <= nb <= 16 and (2 * nb + 1) * sv <= 288
 
-    Matrix: values + column indices + row pointers, each read once; vectors: the
-    gathered input once, n - i columns of Q and the written w_i.  (The input is
-    already in its column of G: the cycle close writes g into G_0 itself.)  The
-    transpose-free steps read columns 0..i-1 of Q instead (v = A g with q_s^H v,
-    s < i): the same count over a cycle, so the same average.  In the literal
-    recurrence order only c_i = q_i^H w_i is reduced: one column of Q.
+
+def spmv_step_bytes(nnz, nbrows, N, n, sv, bsr=False, literal=False, transpose_free=False):
+    """Algorithmic bytes of one SpMV-step launch (w_i = A g_i with its shadow dots), averaged over the
+    launches i = 0..n-1 of one cycle.
+
+    Matrix: values + column indices + row pointers, each read once; vectors: the gathered input once,
+    the columns of Q the epilogue reduces against, and the written w_i.  (The input is already in its
+    column of G: the cycle close writes g into G_0 itself.)  With the S column from the alpha pass
+    (n <= 16, A^H) and in the literal recurrence order the step reduces only c_i: one column of Q.
+    Otherwise it reads n - i columns (s = i..n-1); the transpose-free steps read columns 0..i-1
+    instead (v = A g with q_s^H v, s < i): the same count over a cycle, so the same average.
     """
     mat = nnz * ((9 if bsr else 1) * sv + 4) + 4 * (nbrows + 1)
-    vec_avg = 3.0 if literal else sum(1 + (n - i) + 1 for i in range(n)) / n
+    one = literal or s_from_alpha(n, transpose_free, sv=sv)
+    vec_avg = 3.0 if one else sum(1 + (n - i) + 1 for i in range(n)) / n
     return mat + vec_avg * N * sv
 
 
@@ -53,29 +63,31 @@ def matrix_bytes(nnz, nbrows, sv, bsr=False):
     return nnz * ((9 if bsr else 1) * sv + 4) + 4 * (nbrows + 1)
 
 
-def vector_passes_per_iter(n, transpose_free=False):
+def vector_passes_per_iter(n, transpose_free=False, sv=8):
     """Vectors of N values the kernels of one iteration read or write, averaged over a cycle of n steps
     (the SpMV's gathered input and output included; each vector counted once per pass).
 
     Per inner step i = 1..n-1: alpha pass 6 + n - i, combination 2 + 2(n - i) + i, recombination
     2 + i, SpMV step 2 + (n - i); per cycle end: half step 6, SpMV of the minimisation step 2, omega
-    pass 5 + n, cycle close 2 + 2n, SpMV step 2 + n.  Transpose-free steps replace the recombination and
-    the product of g_k by the product of g (2 + i, its shadow dots) and the recombination of g and w
-    (4 + 2i + n - i), and read no F (combination 2 + 2(n - i))."""
+    pass 5 + n, cycle close 2 + 2n, SpMV step 2 + n.  With the S column from the alpha pass
+    (s_from_alpha) every SpMV step reads one column of Q: 3.  Transpose-free steps replace the
+    recombination and the product of g_k by the product of g (2 + i, its shadow dots) and the
+    recombination of g and w (4 + 2i + n - i), and read no F (combination 2 + 2(n - i))."""
+    one = s_from_alpha(n, transpose_free, sv=sv)
     total = 0
     for i in range(1, n):
         if transpose_free:
             total += (6 + n - i) + (2 + 2 * (n - i)) + (2 + i) + (4 + 2 * i + n - i)
         else:
-            total += (6 + n - i) + (2 + 2 * (n - i) + i) + (2 + i) + (2 + n - i)
-    total += 6 + 2 + (5 + n) + (2 + 2 * n) + (2 + n)
+            total += (6 + n - i) + (2 + 2 * (n - i) + i) + (2 + i) + (3 if one else 2 + n - i)
+    total += 6 + 2 + (5 + n) + (2 + 2 * n) + (3 if one else 2 + n)
     return total / n
 
 
 def bytes_per_iter(nnz, nbrows, N, n, sv, bsr=False, transpose_free=False):
     """Algorithmic bytes of one iteration of the kernels as built: (1 + 1/n) passes over A plus the
     vector passes above."""
-    return (1 + 1 / n) * matrix_bytes(nnz, nbrows, sv, bsr) + vector_passes_per_iter(n, transpose_free) * N * sv
+    return (1 + 1 / n) * matrix_bytes(nnz, nbrows, sv, bsr) + vector_passes_per_iter(n, transpose_free, sv) * N * sv
 
 
 def copy_rate_gbs(torch, dev, gib=1.0, reps=5):
@@ -543,7 +555,8 @@ def main():
     # value bytes of the iteration that the timed kernel belongs to (fp32 inner iteration for ir)
     sv = (16 if cplx else 8) if args.precision == "fp64" else (8 if cplx else 4)
     ms_spmv = solver.time_kernel(binding.MLB_KERNEL_SPMV_STEP, args.kernel_reps)
-    bytes_spmv = spmv_step_bytes(nnz, nbrows, p.N, p.n, sv, bsr=(fmt == "bsr3"), literal=(args.order == "literal"))
+    bytes_spmv = spmv_step_bytes(nnz, nbrows, p.N, p.n, sv, bsr=(fmt == "bsr3"), literal=(args.order == "literal"),
+                                 transpose_free=args.transpose_free)
     achieved = bytes_spmv / (ms_spmv * 1e-3) / 1e9
     ms_alpha = solver.time_kernel(binding.MLB_KERNEL_ALPHA_STEP, args.kernel_reps)
     ms_comb = solver.time_kernel(binding.MLB_KERNEL_COMBINE, args.kernel_reps)

@@ -407,7 +407,7 @@ struct Timed {
       kernel<<<grid, BLOCK, 0, stream>>>(__VA_ARGS__);                                                 \
   } while (0)
 
-static int bucket(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
+static int bucket(int n) { return bucket_of(n); }
 
 // Launches the SpMV kernel for A's format and lanes-per-row with epilogue MODE.
 // With grid == 0 nothing is launched and the kernel's occupancy (workgroups per
@@ -518,6 +518,16 @@ struct Engine {
   const IluFactor<V>* ilu = nullptr;
   V* tpre = nullptr;
   bool literal = false;   // beta~ and beta recurrences in the sequential order, one reduction per coefficient
+  // The S column of w_i below its diagonal from the next alpha pass (PH_INNER_S)
+  // instead of the SpMV step, which then reduces c_i alone (PH_SPMV_C).  It saves
+  // the SpMV epilogue n - i - 1 columns of Q (the alpha pass reads them anyway)
+  // but doubles the sums the alpha pass reduces per workgroup.  Set by set_n for
+  // the Gram-form steps with A^H where that measured faster: a bucket of 8 or 16
+  // whose 2 nb + 1 alpha accumulators stay within 288 bytes (real n <= 16,
+  // complex n <= 8).  At n <= 4 the column is at most 3 entries long and the
+  // wider reduction costs more than the saved reads; complex n = 16 would need
+  // 154 VGPRs in the alpha pass.
+  bool s_alpha = false;
 
   // ext_flag: a pinned, host-mapped int the caller owns (serving workers reuse one
   // per worker); NULL = allocate one.
@@ -565,6 +575,7 @@ struct Engine {
   void set_n(int n_) {
     n = n_;
     nb = bucket(n);
+    s_alpha = !literal && !tf && nb >= 8 && nb <= 16 && (2 * nb + 1) * (int)sizeof(V) <= 288;
     const int cus = device_cus();
     SpmvArgs<V> probe{};
     int occ = 4;
@@ -718,7 +729,8 @@ struct Engine {
 #undef MLB_GW
     scalar(grid_vec, nb, n - i, PH_SPMV_STEP, i, 0);
   }
-  // w_i = A G_i ; S[s][i] = q_s^H w_i, s = i..n-1.  With gin != G_i the input is
+  // w_i = A G_i ; S[s][i] = q_s^H w_i, s = i..n-1 (s = i only with s_alpha: the
+  // rest comes from the next alpha pass).  With gin != G_i the input is
   // also copied to G_i (cycle close and set-up, where g_k = g).
   // The literal order needs only c_i = q_i^H w_i (nd = 1).
   void spmv_step(const V* gin, int i, int flags = 0) {
@@ -726,32 +738,47 @@ struct Engine {
     a.format = A.format; a.nrows = A.nrows; a.nbrows = A.nbrows; a.rp = A.rp; a.ci = A.ci; a.val = A.val;
     V* Gi = G + (size_t)i * N;
     a.xin = pre(gin); a.xown = gin; a.out1 = W + (size_t)i * N; a.out2 = gin == Gi ? nullptr : Gi;
-    a.Q = Q; a.ldq = ldq; a.d0 = i; a.nd = literal ? 1 : n - i;
+    a.Q = Q; a.ldq = ldq; a.d0 = i; a.nd = literal || s_alpha ? 1 : n - i;
     flags |= force_flags;
     const Timed tm = timed(MLB_KERNEL_SPMV_STEP);
-    switch (nb) {
+    const int nbs = s_alpha ? 4 : nb;   // one dot column: the smallest accumulator set
+    switch (nbs) {
       case 4: launch_spmv_nd<V, Sc, SM_STEP, 4>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
       case 8: launch_spmv_nd<V, Sc, SM_STEP, 8>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
       case 16: launch_spmv_nd<V, Sc, SM_STEP, 16>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
       default: launch_spmv_nd<V, Sc, SM_STEP, 32>(A, grid_spmv, s, st, part, a, PH_SPMV_STEP, i, 0, n, flags, tm); break;
     }
-    if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, std::max(nb, 3), a.nd, PH_SPMV_STEP, i, 0);
+    if (!(flags & F_SKIP_SCALAR)) scalar(grid_spmv, std::max(nbs, 3), a.nd, s_alpha ? PH_SPMV_C : PH_SPMV_STEP, i, 0);
   }
   void alpha(V* x, int i_prev, int d0, int nd, int phase, int i, int j, V* xrec, long long K, int flags = 0) {
     const V* gh = G + (size_t)i_prev * N;
     const V* w = W + (size_t)i_prev * N;
     flags |= force_flags;
     const Timed tm = timed(MLB_KERNEL_ALPHA_STEP);
-#define MLB_ALPHA(B) \
-  MLB_LAUNCH((k_alpha<V, Sc, B>), grid_vec, s, tm, st, part, N, x, gh, r, w, Q, ldq, d0, nd, xrec, K, phase, i, j, n, flags)
-    switch (nb) {
-      case 4: MLB_ALPHA(4); break;
-      case 8: MLB_ALPHA(8); break;
-      case 16: MLB_ALPHA(16); break;
-      default: MLB_ALPHA(32); break;
+    // inner steps of the Gram form: also the S column of w = w_{i-1} (PH_INNER_S)
+    const bool sw = s_alpha && phase == PH_INNER;
+#define MLB_ALPHA(B, SW)                                                                                      \
+  MLB_LAUNCH((k_alpha<V, Sc, B, SW>), grid_vec, s, tm, st, part, N, x, gh, r, w, Q, ldq, d0, nd, xrec, K, phase, i, j, \
+             n, flags)
+    if (sw) {
+      switch (nb) {
+        case 4: MLB_ALPHA(4, true); break;
+        case 8: MLB_ALPHA(8, true); break;
+        default: MLB_ALPHA(16, true); break;
+      }
+    } else {
+      switch (nb) {
+        case 4: MLB_ALPHA(4, false); break;
+        case 8: MLB_ALPHA(8, false); break;
+        case 16: MLB_ALPHA(16, false); break;
+        default: MLB_ALPHA(32, false); break;
+      }
     }
 #undef MLB_ALPHA
-    if (!(flags & F_SKIP_SCALAR)) scalar(grid_vec, nb + 1, nd + 1, phase, i, j);
+    if (!(flags & F_SKIP_SCALAR)) {
+      if (sw) scalar(grid_vec, 2 * nb + 1, 1 + nb + nd, PH_INNER_S, i, j);
+      else scalar(grid_vec, nb + 1, nd + 1, phase, i, j);
+    }
   }
   // out: gt (inner steps) or G_0 (cycle close)
   // phase / pi: the recurrence run on the f_s^H g sums (the literal order takes
@@ -841,8 +868,9 @@ struct Engine {
       return;
     }
     for (int i = 1; i < n; ++i) {
-      // x_{jn+i} = x + alpha g ; r_{jn+i} = r - alpha w ; e = q_{i+1}^H r (and q_s^H r, s > i, when j >= 1)
-      alpha(x, i - 1, i, j >= 1 ? n - i : 1, PH_INNER, i, j, xrec, K);
+      // x_{jn+i} = x + alpha g ; r_{jn+i} = r - alpha w ; e = q_{i+1}^H r (and q_s^H r, s > i, when j >= 1;
+      // with s_alpha also q_s^H w_{jn+i-1}, s >= i, at every j)
+      alpha(x, i - 1, i, j >= 1 || s_alpha ? n - i : 1, PH_INNER, i, j, xrec, K);
       if (tf) {
         // g = z_w - g/omega (j >= 1) or r (j = 0); v = A g and the beta recurrence from
         // q_s^H v; g_{jn+i}, w_{jn+i} = v + sum beta_s w_s, c and S column i
@@ -858,7 +886,7 @@ struct Engine {
       // g = z_w - g/omega from the previous cycle's columns (j >= 1), or g = r (j = 0); f_s^H g, s < i
       if (j >= 1) combine(i, n, i, i, j, gt);
       else combine(i, i, i, i, j, gt);
-      // g_{jn+i} = g + sum beta_s g_s ; w_{jn+i} = A g_{jn+i} ; c and S column i
+      // g_{jn+i} = g + sum beta_s g_s ; w_{jn+i} = A g_{jn+i} ; c (and S column i without s_alpha)
       gcomb(gt, i);
       spmv_step(G + (size_t)i * N, i);
     }

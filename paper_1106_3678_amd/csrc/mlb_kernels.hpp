@@ -16,8 +16,13 @@
 //     t_s = -(q_s^H r + sum_{i<=u<s} t_u S[s][u]) / c_s
 //   beta (columns s = 0..i-1 of this cycle):
 //     b_s = -(f_s^H g + sum_{u<s} b_u S[s][u]) / c_s
-// where S[s][u] = q_s^H w_u is produced by the SpMV pass that made w_u (its
-// diagonal is c_u), and f_s^H g_u = q_s^H A g_u = q_s^H w_u (f_s = A^H q_s).
+// where S[s][u] = q_s^H w_u and f_s^H g_u = q_s^H A g_u = q_s^H w_u
+// (f_s = A^H q_s).  The diagonal c_u comes from the SpMV pass that made w_u
+// (the next alpha needs it); the entries below it (s > u) from the next alpha
+// pass, which reads w_u and the same columns q_s (for q_s^H r) anyway, so the
+// SpMV pass reads one column of Q instead of n - u.  Every S[s][u] is first
+// used by a recurrence after that alpha pass: beta~ at step i reads columns
+// u >= i of the previous cycle, beta at step i columns u <= i - 2.
 // Then one pass forms g = r + sum t_s w_s - (1/omega) sum t_s g_s, a second
 // forms g_k = g + sum b_s g_s, and the SpMV pass forms w_k = A g_k from the
 // stored g_k (a fresh product: recombining old w columns instead would save
@@ -75,8 +80,14 @@ enum Phase : int {
   // the sequential (literal) order of the recurrences: one coefficient per reduction
   PH_LIT_T = 8,       // after a beta~ pass: t_i = -(q_i^H z_w) / c_i (i = the coefficient's index)
   PH_LIT_B = 9,       // after a beta pass: beta_i = -(f_i^H g) / c_i
-  PH_OMEGA_LIT = 10   // as PH_OMEGA_UPD, without the beta~ list (computed pass by pass)
+  PH_OMEGA_LIT = 10,  // as PH_OMEGA_UPD, without the beta~ list (computed pass by pass)
+  PH_INNER_S = 11,    // as PH_INNER, and the S column of w_{i-1} below its diagonal
+  PH_SPMV_C = 12      // as PH_SPMV_STEP with only c (the rest of the S column: next PH_INNER_S)
 };
+
+// The shadow-vector count a pass is compiled for (the bucket of n): the
+// number of dot columns of its accumulators.
+__host__ __device__ constexpr int bucket_of(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
 
 // Everything the recurrences need, resident in device memory.  Written only
 // by k_scalar and read by every later pass.
@@ -253,7 +264,13 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       else if (err < st->tol) finish(st, 0);
       break;
     }
+    case PH_INNER_S:
     case PH_INNER: {
+      if (phase == PH_INNER_S) {
+        // sums[1 + bucket + l] = q_{i+l}^H w_{i-1}, l = 0..n-i-1 (k_alpha with SW)
+        const int l = threadIdx.x % WAVE;
+        if (l < n - i) st->S[(i + l) * NMAX + (i - 1)] = sums[1 + bucket_of(n) + l];
+      }
       const long long k = st->iter + 1;
       double err = sqrt(re(sums[0])) / st->bnrm2;
       if (w0) {
@@ -289,9 +306,10 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (s < i) st->beta[s] = b;
       break;
     }
+    case PH_SPMV_C:
     case PH_SPMV_STEP: {
       const int l = threadIdx.x % WAVE;
-      if (i + l < n) st->S[(i + l) * NMAX + i] = sums[l];
+      if (i + l < n && (l == 0 || phase == PH_SPMV_STEP)) st->S[(i + l) * NMAX + i] = sums[l];
       Sc ci = sums[0];
       if (w0) st->c[i] = ci;
       if (is_zero(ci) || !finite(ci)) { finish(st, -1); break; }
@@ -464,17 +482,20 @@ __global__ __launch_bounds__((sblock<Sc, STRIDE>())) void k_scalar(State<Sc>* st
 // ---------------------------------------------------------------- vector passes
 
 // x += alpha gh ; r -= alpha w ; sums: ||r||^2, q_s^H r for s in [d0, d0+nd).
+// SW: also q_s^H w for the same s (the S column of w below its diagonal), at
+// sums[1 + ND + d]; the partial rows are then 2 ND + 1 long.
 // With xrec, x_k is also stored in column k-1 of the iterate record.
-template <class V, class Sc, int ND>
+template <class V, class Sc, int ND, bool SW>
 __global__ __launch_bounds__(BLOCK) void k_alpha(State<Sc>* st, Sc* partial, int N, V* __restrict__ x,
                                                  const V* __restrict__ gh, V* __restrict__ r, const V* __restrict__ w,
                                                  const V* __restrict__ Q, long long ldq, int d0, int nd,
                                                  V* __restrict__ xrec, long long K, int phase, int i, int j, int n,
                                                  int flags) {
   if (!(flags & F_IGNORE_DONE) && st->done) return;
-  V acc[ND + 1];
+  constexpr int NACC = SW ? 2 * ND + 1 : ND + 1;
+  V acc[NACC];
 #pragma unroll
-  for (int d = 0; d <= ND; ++d) acc[d] = zero<V>();
+  for (int d = 0; d < NACC; ++d) acc[d] = zero<V>();
   const V al = convert<V>(st->alpha);
   const V mal = convert<V>(zero<Sc>() - st->alpha);
   const long long k = st->iter + 1;
@@ -483,15 +504,20 @@ __global__ __launch_bounds__(BLOCK) void k_alpha(State<Sc>* st, Sc* partial, int
     V xv = axpy(x[row], al, gh[row]);
     x[row] = xv;
     if (rec) rec[row] = xv;
-    V rv = axpy(r[row], mal, w[row]);
+    const V wv = w[row];
+    V rv = axpy(r[row], mal, wv);
     r[row] = rv;
     cdot_acc(acc[0], rv, rv);
 #pragma unroll
     for (int d = 0; d < ND; ++d)
-      if (d < nd) cdot_acc(acc[1 + d], Q[row + (long long)(d0 + d) * ldq], rv);
+      if (d < nd) {
+        const V qv = Q[row + (long long)(d0 + d) * ldq];
+        cdot_acc(acc[1 + d], qv, rv);
+        if constexpr (SW) cdot_acc(acc[1 + ND + d], qv, wv);
+      }
   }
   if (flags & F_SKIP_SCALAR) return;
-  block_partials<ND + 1>(acc, nd + 1, partial);
+  block_partials<NACC>(acc, SW ? 1 + ND + nd : nd + 1, partial);
 }
 
 // g = r + sum_{s in [t0, n)} (t_s W_s + tg_s G_s) -> gout ; sums: f_s^H g, s < nf.

@@ -7,13 +7,20 @@ import bench
 
 
 def test_spmv_step_bytes_by_hand():
-    # CSR: 10 entries, 4 rows, n = 2: matrix 10 * (8 + 4) + 4 * 5 = 140 B; vectors per launch
-    # (input + n - i columns of Q + output), i = 0, 1: 4 and 3, mean 3.5 vectors of 32 B
+    # CSR: 10 entries, 4 rows: matrix 10 * (8 + 4) + 4 * 5 = 140 B.  n = 2 (S column in the SpMV
+    # epilogue): input + n - i columns of Q + output, i = 0, 1: 4 and 3, mean 3.5 vectors of 32 B
     assert bench.spmv_step_bytes(10, 4, 4, 2, 8) == 140 + 3.5 * 32
+    # n = 8 real: the S column comes from the alpha pass, the step reads one column of Q: 3 vectors
+    assert bench.spmv_step_bytes(10, 4, 4, 8, 8) == 140 + 3 * 32
+    # transpose-free n = 8: 2 + 8 - i, i = 0..7: 10 + 9 + ... + 3 = 52, mean 6.5
+    assert bench.spmv_step_bytes(10, 4, 4, 8, 8, transpose_free=True) == 140 + 6.5 * 32
+    # complex values double the value bytes; n = 8 keeps the alpha-pass S column (17 x 16 B <= 288 B),
+    # n = 16 does not (33 x 16 B): 3 + 4 + ... + 18 = 168 over 16 launches
+    assert bench.spmv_step_bytes(10, 4, 4, 8, 16) == 10 * 20 + 20 + 3 * 64
+    assert bench.spmv_step_bytes(10, 4, 4, 16, 16) == 10 * 20 + 20 + 10.5 * 64
+    assert bench.spmv_step_bytes(10, 4, 4, 20, 8) == 140 + (sum(2 + 20 - i for i in range(20)) / 20) * 32
     # BSR3: 2 blocks, 2 block rows (N = 6), n = 1: 2 * (72 + 4) + 4 * 3 = 164 B; 3 vectors of 48 B
     assert bench.spmv_step_bytes(2, 2, 6, 1, 8, bsr=True) == 164 + 3 * 48
-    # complex values double the value bytes only
-    assert bench.spmv_step_bytes(10, 4, 4, 2, 16) == 10 * 20 + 20 + 3.5 * 64
 
 
 def _tree(tmp_path, src_text, recorded_hash, traffic=12345):
@@ -70,9 +77,15 @@ def test_cpu_baseline_sample_is_bounded():
 
 def test_vector_passes_by_hand():
     """n = 2: inner step i = 1 moves (6 + 1) + (2 + 2 + 1) + (2 + 1) + (2 + 1) = 18 vectors, the cycle end
-    6 + 2 + 7 + 6 + 4 = 25; 43 per cycle of 2 iterations.  n = 1 (BiCGStab): 21 per iteration."""
+    6 + 2 + 7 + 6 + 4 = 25; 43 per cycle of 2 iterations.  n = 1 (BiCGStab): 21 per iteration.
+    n = 8 (S column from the alpha pass, every SpMV step 3 vectors): inner steps
+    (14 - i) + (18 - i) + (2 + i) + 3 = 37 - i, i = 1..7: 231; cycle end 6 + 2 + 13 + 18 + 3 = 42;
+    273 per cycle, n(n - 1)/2 = 28 fewer than with the S column in the SpMV epilogue."""
     assert bench.vector_passes_per_iter(2) == 43 / 2
     assert bench.vector_passes_per_iter(1) == 21
+    assert bench.vector_passes_per_iter(8) == 273 / 8
+    assert bench.vector_passes_per_iter(8, sv=16) == 273 / 8
+    assert bench.vector_passes_per_iter(16, sv=16) * 16 - bench.vector_passes_per_iter(16) * 16 == 16 * 15 / 2
     # transpose-free, n = 2: (6 + 1) + (2 + 2) + (2 + 1) + (4 + 2 + 1) = 21 per inner step
     assert bench.vector_passes_per_iter(2, transpose_free=True) == (21 + 25) / 2
 
@@ -82,4 +95,5 @@ def test_spmv_step_bytes_literal_order():
     nnz, N, n, sv = 7000, 1000, 8, 8
     mat = nnz * (sv + 4) + 4 * (N + 1)
     assert bench.spmv_step_bytes(nnz, N, N, n, sv, literal=True) == mat + 3 * N * sv
-    assert bench.spmv_step_bytes(nnz, N, N, n, sv) > bench.spmv_step_bytes(nnz, N, N, n, sv, literal=True)
+    assert bench.spmv_step_bytes(nnz, N, N, n, sv, literal=True, transpose_free=True) == mat + 3 * N * sv
+    assert bench.spmv_step_bytes(nnz, N, N, n, sv, transpose_free=True) > mat + 3 * N * sv

@@ -199,8 +199,10 @@ def test_csr_point_jacobi(n):
     check_parity(workloads.config5(n=n, m=12, maxit=4000), precond=1)
 
 
-@pytest.mark.parametrize("n", [4, 16])
+@pytest.mark.parametrize("n", [4, 6, 8, 16])
 def test_complex_small(n):
+    """Complex shifted Helmholtz, N = 1728.  n = 6 and 8 take the S column of each w below its diagonal
+    from the next alpha pass; n = 4 and 16 from the SpMV step's epilogue."""
     check_parity(workloads.config5(n=n, m=12, maxit=4000))
 
 
