@@ -236,6 +236,11 @@ def serving_items(args, torch, workloads, binding):
     return reqs, items
 
 
+def serve_order(args, binding):
+    """The server's pick order for the workers' queue (--serve-order)."""
+    return binding.MLB_SERVE_SMALLEST if getattr(args, "serve_order", "fifo") == "smallest" else binding.MLB_SERVE_FIFO
+
+
 def bench_serving(args, torch, workloads, binding, generated=None, sequential=True):
     """Continuous batching of a Poisson stream of uneven solves (tol 1e-10; --serve-precision picks fp32
     inner / fp64 refinement, as the serving configuration names, or fp64)."""
@@ -251,7 +256,7 @@ def bench_serving(args, torch, workloads, binding, generated=None, sequential=Tr
     torch.cuda.synchronize()
 
     server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight,
-                            small_n_max=args.small_n_max)
+                            small_n_max=args.small_n_max, order=serve_order(args, binding))
     t0 = time.perf_counter()
     tickets = []
     for r, p, dA, b, x, Q in items:
@@ -278,7 +283,7 @@ def bench_serving(args, torch, workloads, binding, generated=None, sequential=Tr
         it[4].zero_()
     torch.cuda.synchronize()
     server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight,
-                            small_n_max=args.small_n_max)
+                            small_n_max=args.small_n_max, order=serve_order(args, binding))
     t2 = time.perf_counter()
     tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit, precision=prec,
                              transpose_free=args.transpose_free)
@@ -313,6 +318,7 @@ def bench_serving(args, torch, workloads, binding, generated=None, sequential=Tr
                    "arrival_rate_per_s": 200.0, "N_range": [int(min(r.N for r in reqs)), int(max(r.N for r in reqs))],
                    "inflight": args.inflight, "budget_gb": args.budget_gb, "tol": 1e-10,
                    "small_n_max": args.small_n_max,
+                   "order": "smallest footprint first (max wait 1 s)" if serve_order(args, binding) else "fifo",
                    "variant": "transpose-free (no A^H)" if args.transpose_free else "Algorithm 7.1 (explicit A^H)",
                    "all_converged": bool(all(f == 0 for f in flags)), "max_err_true": float(max(errs)),
                    "total_iterations": int(sum(iters))},
@@ -357,7 +363,7 @@ def bench_serving_sequences(args, torch, workloads, binding):
             it[3].zero_()
         torch.cuda.synchronize()
         server = binding.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_inflight=args.inflight,
-                                small_n_max=args.small_n_max)
+                                small_n_max=args.small_n_max, order=serve_order(args, binding))
         t0 = time.perf_counter()
         tickets = []
         for mi, at, b, x in items:
@@ -482,6 +488,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM admission budget")
     ap.add_argument("--small-n-max", type=int, default=0,
                     help="serving: largest N batched in one-workgroup launches (0 = library default, -1 = none)")
+    ap.add_argument("--serve-order", default="fifo", choices=["fifo", "smallest"],
+                    help="serving: the workers' pick order (smallest: smallest footprint first, 1 s max wait)")
     ap.add_argument("--serve-precision", default="ir", choices=["fp64", "ir"],
                     help="serving: iteration precision (the serving configuration names fp32-IR)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "ir"])

@@ -331,9 +331,16 @@ enum {
  * batchers; a free batcher takes every waiting small request that fits (at
  * most 256) and solves them in one launch of mlbicgstab_solve_batch's kernel.
  * Other requests wait for the workers, which run create, solve and destroy
- * one request at a time.  Both queues are first-in first-out: the oldest
- * waiting request starts as soon as a worker (batcher) is free and its device
- * footprint (mlbicgstab_workspace_size) fits the unused part of budget_bytes.
+ * one request at a time.  The batchers' queue is first-in first-out.  The
+ * workers' queue is too by default (order MLB_SERVE_FIFO): the oldest waiting
+ * request starts as soon as a worker is free and its device footprint
+ * (mlbicgstab_workspace_size) fits the unused part of budget_bytes.  With
+ * MLB_SERVE_SMALLEST a free worker takes the waiting request of smallest
+ * footprint that fits (the oldest among equal footprints, so a sequence keeps
+ * its order), except that a request which has waited max_wait_ms or longer
+ * goes first, oldest first, and holds the queue until its footprint fits: under
+ * load small solves then no longer wait behind large ones, and no request
+ * waits much beyond max_wait_ms plus the runs in flight.
  * Requests that arrive while others run therefore start as slots and memory
  * free up, and their kernels overlap on the device.  A solve gives the same
  * result whatever else is in flight (same grids and reduction order; the
@@ -350,8 +357,13 @@ typedef struct {
   int32_t small_n_max;      /* CSR fp64 requests without preconditioner and with
                                at most this many rows go to the batchers
                                (0: MLB_SERVER_SMALL_N, -1: none)              */
+  int32_t order;            /* workers' pick order: MLB_SERVE_FIFO or MLB_SERVE_SMALLEST */
+  double max_wait_ms;       /* MLB_SERVE_SMALLEST: age at which a request goes
+                               first (0: MLB_SERVER_MAX_WAIT_MS)                */
 } mlb_server_options;
 #define MLB_SERVER_SMALL_N 4096
+enum { MLB_SERVE_FIFO = 0, MLB_SERVE_SMALLEST = 1 };
+#define MLB_SERVER_MAX_WAIT_MS 1000.0
 
 typedef struct {
   double queued_ms;         /* submit -> start                                  */

@@ -24,6 +24,7 @@ MLB_OP_A, MLB_OP_AH = 0, 1
 MLB_MAX_N = 32
 MLB_MAX_INDEX = 2 ** 31 - 2 ** 20   # largest nrows and nnz
 MLB_KERNEL_SPMV_STEP, MLB_KERNEL_ALPHA_STEP, MLB_KERNEL_COMBINE, MLB_KERNEL_RECOMBINE = 0, 1, 2, 3
+MLB_SERVE_FIFO, MLB_SERVE_SMALLEST = 0, 1
 
 
 class mlb_matrix(ctypes.Structure):
@@ -69,7 +70,8 @@ class mlb_result(ctypes.Structure):
 
 
 class mlb_server_options(ctypes.Structure):
-    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32), ("small_n_max", ctypes.c_int32)]
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32), ("small_n_max", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("max_wait_ms", ctypes.c_double)]
 
 
 class mlb_request_timing(ctypes.Structure):
@@ -258,9 +260,11 @@ def mlb_sequence_destroy(h) -> int:
     return _check(_lib.mlb_sequence_destroy(h))
 
 
-def mlb_server_create(budget_bytes: int, max_inflight: int, small_n_max: int = 0):
+def mlb_server_create(budget_bytes: int, max_inflight: int, small_n_max: int = 0, order: int = MLB_SERVE_FIFO,
+                      max_wait_ms: float = 0.0):
     h = mlb_server_handle()
-    _check(_lib.mlb_server_create(ctypes.byref(mlb_server_options(budget_bytes, max_inflight, small_n_max)),
+    _check(_lib.mlb_server_create(ctypes.byref(mlb_server_options(budget_bytes, max_inflight, small_n_max, order,
+                                                                  max_wait_ms)),
                                   ctypes.byref(h)))
     return h
 
@@ -492,8 +496,9 @@ class Sequence:
 class Server:
     """Continuous-batching front end: submit() solves, wait()/poll() for their results."""
 
-    def __init__(self, budget_bytes: int, max_inflight: int = 4, small_n_max: int = 0):
-        self.h = mlb_server_create(budget_bytes, max_inflight, small_n_max)
+    def __init__(self, budget_bytes: int, max_inflight: int = 4, small_n_max: int = 0, order: int = MLB_SERVE_FIFO,
+                 max_wait_ms: float = 0.0):
+        self.h = mlb_server_create(budget_bytes, max_inflight, small_n_max, order, max_wait_ms)
         self._keep = {}
 
     def submit(self, dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,

@@ -1965,6 +1965,8 @@ struct Server {
   std::deque<std::shared_ptr<Request>> queue;        // requests for the workers
   std::deque<std::shared_ptr<Request>> small_queue;  // requests for the batchers
   int small_n_max = 0;                                // largest N a batcher takes (0: none)
+  int order = MLB_SERVE_FIFO;                         // the workers' pick order
+  double max_wait_s = 1.0;                            // MLB_SERVE_SMALLEST: age that goes first
   std::unordered_map<int64_t, std::shared_ptr<Request>> table;
   std::unordered_map<uint64_t, std::shared_ptr<SeqEntry>> seqs;   // live sequences by key
   int64_t next_ticket = 1;
@@ -2018,11 +2020,33 @@ static void run_seq_request(SeqEntry& q, Request& r, hipStream_t st) {
   }
 }
 
-// Whether the head request of the worker queue may start now.
-static bool head_fits(const Server* S) {
-  const Request& r = *S->queue.front();
+// Whether a request of the worker queue may start now (its footprint fits; a
+// sequence's is admitted once, with its first request).
+static bool fits(const Server* S, const Request& r) {
   if (r.seq) return r.seq->busy || r.seq->admitted || S->used + r.seq->footprint <= S->budget;
   return S->used + r.footprint <= S->budget;
+}
+
+// The request a free worker takes next, or queue.end() if none may start now.
+// FIFO: the head, once it fits.  SMALLEST: the oldest request that has waited
+// max_wait_s (it holds the queue until it fits), else the smallest footprint
+// that fits, the oldest among equal ones.
+static std::deque<std::shared_ptr<Request>>::iterator pick(Server* S) {
+  auto& q = S->queue;
+  if (q.empty()) return q.end();
+  if (S->order == MLB_SERVE_FIFO) return fits(S, *q.front()) ? q.begin() : q.end();
+  if (now_s() - q.front()->t_submit >= S->max_wait_s) return fits(S, *q.front()) ? q.begin() : q.end();
+  auto best = q.end();
+  size_t best_fp = 0;
+  for (auto it = q.begin(); it != q.end(); ++it) {
+    const Request& r = **it;
+    const size_t fp = r.seq ? r.seq->footprint : r.footprint;
+    if ((best == q.end() || fp < best_fp) && fits(S, r)) {
+      best = it;
+      best_fp = fp;
+    }
+  }
+  return best;
 }
 
 // Whether a request of sequence q still waits in the worker queue.
@@ -2049,10 +2073,17 @@ static void worker_main(Server* S) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
       while (true) {
-        S->cv_work.wait(lk, [&] { return (S->stopping && S->queue.empty()) || (!S->queue.empty() && head_fits(S)); });
+        // (age alone never makes a request startable: when none fits, only a
+        // completion or a submission changes that, and both notify)
+        auto it = S->queue.end();
+        S->cv_work.wait(lk, [&] {
+          if (S->stopping && S->queue.empty()) return true;
+          it = pick(S);
+          return it != S->queue.end();
+        });
         if (S->queue.empty()) break;   // stopping and drained
-        r = S->queue.front();
-        S->queue.pop_front();
+        r = *it;
+        S->queue.erase(it);
         if (r->seq && r->seq->busy) {   // its sequence runs on another worker, which takes it next
           r->seq->pending.push_back(r);
           r.reset();
@@ -2269,10 +2300,15 @@ int mlb_server_create(const mlb_server_options* o, mlb_server_handle* out) {
     if (o->max_inflight < 1 || o->max_inflight > 64) throw Error{MLB_EINVAL, "max_inflight must be in [1, 64]"};
     if (o->small_n_max < -1 || o->small_n_max > MLB_BATCH_MAX_N)
       throw Error{MLB_EINVAL, "small_n_max must be -1, 0 or at most MLB_BATCH_MAX_N"};
+    if (o->order != MLB_SERVE_FIFO && o->order != MLB_SERVE_SMALLEST)
+      throw Error{MLB_EINVAL, "order must be MLB_SERVE_FIFO or MLB_SERVE_SMALLEST"};
+    if (!(o->max_wait_ms >= 0.0) || !(o->max_wait_ms < 1e12)) throw Error{MLB_EINVAL, "max_wait_ms must be in [0, 1e12)"};
     auto S = std::make_unique<mlb_server>();
     S->budget = o->budget_bytes;
     S->max_inflight = o->max_inflight;
     S->small_n_max = o->small_n_max == 0 ? MLB_SERVER_SMALL_N : std::max(o->small_n_max, 0);
+    S->order = o->order;
+    S->max_wait_s = (o->max_wait_ms > 0.0 ? o->max_wait_ms : MLB_SERVER_MAX_WAIT_MS) * 1e-3;
     HIP_TRY(hipGetDevice(&S->device));
     // keep freed stream-ordered memory cached in the pool between requests
     hipMemPool_t pool;

@@ -140,9 +140,12 @@ def test_workspace_size_transpose_free(binding, n, dtype, fmt):
 
 def test_server_rejects_bad_options(binding):
     h = binding.mlb_server_handle()
-    for budget, inflight, small in [(0, 4, 0), (1 << 30, 0, 0), (1 << 30, 65, 0), (1 << 30, 4, -2),
-                                    (1 << 30, 4, (1 << 18) + 1)]:
-        o = binding.mlb_server_options(budget, inflight, small)
+    for budget, inflight, small, order, wait in [(0, 4, 0, 0, 0.0), (1 << 30, 0, 0, 0, 0.0), (1 << 30, 65, 0, 0, 0.0),
+                                                 (1 << 30, 4, -2, 0, 0.0), (1 << 30, 4, (1 << 18) + 1, 0, 0.0),
+                                                 (1 << 30, 4, 0, 2, 0.0), (1 << 30, 4, 0, -1, 0.0),
+                                                 (1 << 30, 4, 0, 1, -1.0), (1 << 30, 4, 0, 1, float("nan")),
+                                                 (1 << 30, 4, 0, 1, float("inf"))]:
+        o = binding.mlb_server_options(budget, inflight, small, order, wait)
         assert binding.raw_call("mlb_server_create", ctypes.byref(o), ctypes.byref(h)) == binding.MLB_EINVAL
         assert h.value is None
     assert binding.raw_call("mlb_server_destroy", None) == 0

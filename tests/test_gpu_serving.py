@@ -1,6 +1,8 @@
 """Serving (continuous batching through mlb_server_*): every result in a concurrent mix equals the same
 request served alone, a failing request is isolated, and admission respects the HBM budget.  Small CSR
 fp64 requests go to the batchers (one-workgroup kernel), the others to the multi-launch workers."""
+import time
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -128,6 +130,43 @@ def test_failing_request_is_isolated():
     for (p, prec), (res, _), (_, _, x, _) in zip(items[1:], results[1:], bufs[1:]):
         res_a, x_a = solve_alone(p, prec)
         assert res.flag == 0 and np.array_equal(x.cpu().numpy(), x_a)
+
+
+def test_smallest_first_order():
+    """MLB_SERVE_SMALLEST: with one worker, four large requests and then a small one queued while the first
+    large one runs, the small one waits for at most one large run; under MLB_SERVE_FIFO it waits for the
+    three large ones queued before it, and with a max_wait_ms below the queueing delay every request has
+    aged, so the order is FIFO again.  Every result is bitwise the same in the three orders."""
+    big = [workloads.serving_problem(workloads.Request(i, 0.0, 3, 48, 5.0 + i, 4, 900 + i), maxit=5000)
+           for i in range(4)]
+    small = workloads.serving_problem(workloads.Request(9, 0.0, 2, 20, 3.0, 4, 990), maxit=5000)
+    probs = big + [small]
+    out = {}
+    for tag, order, wait_ms in (("fifo", binding.MLB_SERVE_FIFO, 0.0), ("smallest", binding.MLB_SERVE_SMALLEST, 0.0),
+                                ("aged", binding.MLB_SERVE_SMALLEST, 1e-3)):
+        bufs = [upload(p) for p in probs]
+        torch.cuda.synchronize()
+        server = binding.Server(budget_bytes=8 << 30, max_inflight=1, small_n_max=-1, order=order,
+                                max_wait_ms=wait_ms)
+        t0 = time.perf_counter()
+        tickets = [server.submit(dA, b, x, Q, p.n, tol=p.tol, maxit=p.maxit) for p, (dA, b, x, Q) in zip(probs, bufs)]
+        submit_ms = (time.perf_counter() - t0) * 1e3
+        res = [server.wait(t) for t in tickets]
+        server.close()
+        tims = [r[1] for r in res]
+        print(f"{tag}: submitted in {submit_ms:.2f} ms; queued " +
+              ", ".join(f"{t.queued_ms:.1f}" for t in tims) + " ms; run " + ", ".join(f"{t.run_ms:.1f}" for t in tims),
+              flush=True)
+        assert all(r[0].flag == 0 for r in res)
+        assert submit_ms < min(t.run_ms for t in tims[:4])   # all five queued while the first large one ran
+        out[tag] = ([b[2].cpu().numpy() for b in bufs], tims)
+    f, sm, ag = out["fifo"][1], out["smallest"][1], out["aged"][1]
+    assert f[4].queued_ms >= f[1].run_ms + f[2].run_ms + f[3].run_ms
+    assert sm[4].queued_ms <= max(t.run_ms for t in sm[:4]) + 5.0
+    assert ag[4].queued_ms >= ag[2].run_ms + ag[3].run_ms
+    for k in range(5):
+        assert np.array_equal(out["fifo"][0][k], out["smallest"][0][k])
+        assert np.array_equal(out["fifo"][0][k], out["aged"][0][k])
 
 
 def test_admission_respects_budget():
