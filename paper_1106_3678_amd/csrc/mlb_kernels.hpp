@@ -485,6 +485,10 @@ __global__ __launch_bounds__((sblock<Sc, STRIDE>())) void k_scalar(State<Sc>* st
 // SW: also q_s^H w for the same s (the S column of w below its diagonal), at
 // sums[1 + ND + d]; the partial rows are then 2 ND + 1 long.
 // With xrec, x_k is also stored in column k-1 of the iterate record.
+// All ND column loads of a row are issued together, before any is used: the
+// columns past nd repeat column d0 (cache hits) and feed sums that are never
+// reduced.  Loads under a per-column test are issued one at a time, each
+// waited for (2-4% slower solves at n = 8, 16).  k_omega does the same.
 template <class V, class Sc, int ND, bool SW>
 __global__ __launch_bounds__(BLOCK) void k_alpha(State<Sc>* st, Sc* partial, int N, V* __restrict__ x,
                                                  const V* __restrict__ gh, V* __restrict__ r, const V* __restrict__ w,
@@ -501,20 +505,25 @@ __global__ __launch_bounds__(BLOCK) void k_alpha(State<Sc>* st, Sc* partial, int
   const long long k = st->iter + 1;
   V* rec = (xrec && k <= K) ? xrec + (k - 1) * (long long)N : nullptr;
   for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
-    V xv = axpy(x[row], al, gh[row]);
+    const V gv = gh[row], wv = w[row], x0 = x[row], r0 = r[row];
+    V qv[ND];
+    if (nd > 0) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d) qv[d] = Q[row + (long long)(d0 + (d < nd ? d : 0)) * ldq];
+    }
+    V xv = axpy(x0, al, gv);
     x[row] = xv;
     if (rec) rec[row] = xv;
-    const V wv = w[row];
-    V rv = axpy(r[row], mal, wv);
+    V rv = axpy(r0, mal, wv);
     r[row] = rv;
     cdot_acc(acc[0], rv, rv);
+    if (nd > 0) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
-      if (d < nd) {
-        const V qv = Q[row + (long long)(d0 + d) * ldq];
-        cdot_acc(acc[1 + d], qv, rv);
-        if constexpr (SW) cdot_acc(acc[1 + ND + d], qv, wv);
+      for (int d = 0; d < ND; ++d) {
+        cdot_acc(acc[1 + d], qv[d], rv);
+        if constexpr (SW) cdot_acc(acc[1 + ND + d], qv[d], wv);
       }
+    }
   }
   if (flags & F_SKIP_SCALAR) return;
   block_partials<NACC>(acc, SW ? 1 + ND + nd : nd + 1, partial);
@@ -718,16 +727,18 @@ __global__ __launch_bounds__(BLOCK) void k_omega(State<Sc>* st, Sc* partial, int
   const long long k = st->iter + 1;
   V* rec = (xrec && k <= K) ? xrec + (k - 1) * (long long)N : nullptr;
   for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
-    const V u = r[row];
-    V xv = axpy(x[row], om, u);
+    const V u = r[row], x0 = x[row], zv = z[row];
+    V qv[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) qv[d] = Q[row + (long long)(d < nd ? d : 0) * ldq];
+    V xv = axpy(x0, om, u);
     x[row] = xv;
     if (rec) rec[row] = xv;
-    V rv = axpy(u, mom, z[row]);
+    V rv = axpy(u, mom, zv);
     r[row] = rv;
     cdot_acc(acc[0], rv, rv);
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
-      if (d < nd) cdot_acc(acc[1 + d], Q[row + (long long)d * ldq], rv);
+    for (int d = 0; d < ND; ++d) cdot_acc(acc[1 + d], qv[d], rv);
   }
   if (flags & F_SKIP_SCALAR) return;
   block_partials<ND + 1>(acc, nd + 1, partial);
