@@ -221,9 +221,24 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(State<Sc>* st, Sc* partial, Spmv
       } else if constexpr (MODE == SM_STEP) {
         a.out1[row] = y;
         if (a.out2) a.out2[row] = a.xown[row];
+        if constexpr (ND >= 8) {
+          // columns in groups of 4, the loads of a group issued together (a group's columns
+          // past nd repeat column d0 and feed sums that are never reduced)
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
-          if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
+          for (int d4 = 0; d4 < ND; d4 += 4) {
+            if (d4 < a.nd) {
+              V qv[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) qv[u] = a.Q[row + (long long)(a.d0 + (d4 + u < a.nd ? d4 + u : 0)) * a.ldq];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) cdot_acc(acc[d4 + u], qv[u], y);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < ND; ++d)
+            if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
+        }
       } else {  // SM_OMEGA
         a.out1[row] = y;
         cdot_acc(acc[0], y, y);
@@ -330,9 +345,24 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_bsrw(State<Sc>* st, Sc* partial,
       } else if constexpr (MODE == SM_STEP) {
         a.out1[row] = y;
         if (a.out2) a.out2[row] = a.xown[row];
+        if constexpr (ND >= 8) {
+          // columns in groups of 4, the loads of a group issued together (a group's columns
+          // past nd repeat column d0 and feed sums that are never reduced)
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
-          if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
+          for (int d4 = 0; d4 < ND; d4 += 4) {
+            if (d4 < a.nd) {
+              V qv[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) qv[u] = a.Q[row + (long long)(a.d0 + (d4 + u < a.nd ? d4 + u : 0)) * a.ldq];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) cdot_acc(acc[d4 + u], qv[u], y);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < ND; ++d)
+            if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
+        }
       } else {  // SM_OMEGA
         a.out1[row] = y;
         cdot_acc(acc[0], y, y);
@@ -439,9 +469,24 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_csrw(State<Sc>* st, Sc* partial,
       } else if constexpr (MODE == SM_STEP) {
         a.out1[row] = y;
         if (a.out2) a.out2[row] = a.xown[row];
+        if constexpr (ND >= 8) {
+          // columns in groups of 4, the loads of a group issued together (a group's columns
+          // past nd repeat column d0 and feed sums that are never reduced)
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
-          if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
+          for (int d4 = 0; d4 < ND; d4 += 4) {
+            if (d4 < a.nd) {
+              V qv[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) qv[u] = a.Q[row + (long long)(a.d0 + (d4 + u < a.nd ? d4 + u : 0)) * a.ldq];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) cdot_acc(acc[d4 + u], qv[u], y);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < ND; ++d)
+            if (d < a.nd) cdot_acc(acc[d], a.Q[row + (long long)(a.d0 + d) * a.ldq], y);
+        }
       } else {  // SM_OMEGA
         a.out1[row] = y;
         cdot_acc(acc[0], y, y);
