@@ -413,7 +413,8 @@ def bench_serving_sequences(args, torch, workloads, binding):
 
 def bench_sequence(args, torch, workloads, binding):
     """A sequence of systems with the same A (3D convection-diffusion, new b each time): total solve time
-    with n = 1 (BiCGStab), fixed n, and n chosen from one system to the next (Section 5.2)."""
+    with n = 1 (BiCGStab), fixed n, and n chosen from one system to the next (Section 5.2).  --precond
+    ilu0 runs every variant with ILU(0), the setting of the paper's Section 5.2 measurements."""
     m = args.m or 128
     n_max = 16
     if args.seq_matrix == "reservoir":
@@ -424,14 +425,17 @@ def bench_sequence(args, torch, workloads, binding):
         p = workloads.config2(n=n_max, m=m)
         name = f"sequence_convdiff3d_m{m}_{args.systems}systems"
         pre = binding.MLB_PRECOND_NONE
+    if args.precond == "ilu0":
+        pre = binding.MLB_PRECOND_ILU0
+        name += "_ilu0"
     g = np.random.default_rng(1106)
     rhs = [torch.from_numpy(g.standard_normal(p.N)).cuda() for _ in range(args.systems)]
     dA = binding.to_device(p.A)
     Q = binding.column_major(p.Q)
     x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
     out = {}
-    for name, n0, lo, hi, step in [("bicgstab_n1", 1, 1, 1, 0), ("fixed_n4", 4, 4, 4, 0), ("fixed_n8", 8, 8, 8, 0),
-                                   ("auto_from_n4_step2", 4, 1, n_max, 2)]:
+    for var, n0, lo, hi, step in [("bicgstab_n1", 1, 1, 1, 0), ("fixed_n4", 4, 4, 4, 0), ("fixed_n8", 8, 8, 8, 0),
+                                  ("auto_from_n4_step2", 4, 1, n_max, 2)]:
         seq = binding.Sequence(dA, n0, lo, hi, step, tol=p.tol, maxit=p.maxit, precond=pre)
         Qv = Q[:, :hi]
         x.zero_()
@@ -451,9 +455,9 @@ def bench_sequence(args, torch, workloads, binding):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         seq.close()
-        out[name] = {"solve_ms_total": total, "wall_s": wall, "n_used": used, "iterations": iters,
-                     "max_err_true": max(errs)}
-        log(f"[bench] sequence {name}: {total:.1f} ms over {len(rhs)} systems, n {used}, iterations {iters}")
+        out[var] = {"solve_ms_total": total, "wall_s": wall, "n_used": used, "iterations": iters,
+                    "max_err_true": max(errs)}
+        log(f"[bench] sequence {var}: {total:.1f} ms over {len(rhs)} systems, n {used}, iterations {iters}")
     base = out["bicgstab_n1"]["solve_ms_total"]
     best = min(v["solve_ms_total"] for k, v in out.items() if k != "bicgstab_n1")
     return {
@@ -462,7 +466,8 @@ def bench_sequence(args, torch, workloads, binding):
         "ms_per_step": 1e3 * out["auto_from_n4_step2"]["wall_s"] / len(rhs), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": name, "N": p.N, "tol": p.tol,
-                   "preconditioner": "block Jacobi (right)" if pre else "none"},
+                   "preconditioner": {binding.MLB_PRECOND_NONE: "none", binding.MLB_PRECOND_JACOBI: "block Jacobi (right)",
+                                      binding.MLB_PRECOND_ILU0: "ILU(0) (right)"}[pre]},
         "variants": out,
         "reduction_vs_bicgstab": {k: 1.0 - v["solve_ms_total"] / base for k, v in out.items() if k != "bicgstab_n1"},
         "best_reduction_vs_bicgstab": 1.0 - best / base,
