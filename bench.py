@@ -631,7 +631,10 @@ def main():
             "matrix_setup_ms": run["create_ms"],
         },
         "roofline": {
-            "kernel": "k_spmv_csrw / k_spmv_bsrw / k_spmv (SpMV step: w_i = A g_i with q_s^H w_i, s >= i)",
+            "kernel": "k_spmv_csrw / k_spmv_bsrw / k_spmv (SpMV step: w_i = A g_i with " +
+                      ("c_i = q_i^H w_i only: literal order)" if args.order == "literal" else
+                       "c_i = q_i^H w_i; q_s^H w_i, s > i, in the alpha pass)"
+                       if s_from_alpha(p.n, args.transpose_free, sv=sv) else "q_s^H w_i, s >= i)"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
