@@ -486,9 +486,9 @@ __global__ __launch_bounds__((sblock<Sc, STRIDE>())) void k_scalar(State<Sc>* st
 // sums[1 + ND + d]; the partial rows are then 2 ND + 1 long.
 // With xrec, x_k is also stored in column k-1 of the iterate record.
 // All ND column loads of a row are issued together, before any is used: the
-// columns past nd repeat column d0 (cache hits) and feed sums that are never
-// reduced.  Loads under a per-column test are issued one at a time, each
-// waited for (2-4% slower solves at n = 8, 16).  k_omega does the same.
+// columns past nd repeat column d0 (cache hits) and feed sums that no
+// recurrence reads.  Loads under a per-column test are issued one at a time,
+// each waited for (2-4% slower solves at n = 8, 16).  k_omega does the same.
 template <class V, class Sc, int ND, bool SW>
 __global__ __launch_bounds__(BLOCK) void k_alpha(State<Sc>* st, Sc* partial, int N, V* __restrict__ x,
                                                  const V* __restrict__ gh, V* __restrict__ r, const V* __restrict__ w,
