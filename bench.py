@@ -67,9 +67,11 @@ def vector_passes_per_iter(n, transpose_free=False, sv=8):
     """Vectors of N values the kernels of one iteration read or write, averaged over a cycle of n steps
     (the SpMV's gathered input and output included; each vector counted once per pass).
 
-    Per inner step i = 1..n-1: alpha pass 6 + n - i, combination 2 + 2(n - i) + i, recombination
-    2 + i, SpMV step 2 + (n - i); per cycle end: half step 6, SpMV of the minimisation step 2, omega
-    pass 5 + n, cycle close 2 + 2n, SpMV step 2 + n.  With the S column from the alpha pass
+    The solves bench.py times record no iterates, so the x updates of a cycle are deferred to the omega
+    pass.  Per inner step i = 1..n-1: alpha pass 3 + n - i (r, w, n - i columns of Q, r written),
+    combination 2 + 2(n - i) + i, recombination 2 + i, SpMV step 2 + (n - i); per cycle end: half step
+    3, SpMV of the minimisation step 2, omega pass 5 + 2n (x, u, z, n columns of Q and n of G; x and r
+    written), cycle close 2 + 2n, SpMV step 2 + n.  With the S column from the alpha pass
     (s_from_alpha) every SpMV step reads one column of Q: 3.  Transpose-free steps replace the
     recombination and the product of g_k by the product of g (2 + i, its shadow dots) and the
     recombination of g and w (4 + 2i + n - i), and read no F (combination 2 + 2(n - i))."""
@@ -77,10 +79,10 @@ def vector_passes_per_iter(n, transpose_free=False, sv=8):
     total = 0
     for i in range(1, n):
         if transpose_free:
-            total += (6 + n - i) + (2 + 2 * (n - i)) + (2 + i) + (4 + 2 * i + n - i)
+            total += (3 + n - i) + (2 + 2 * (n - i)) + (2 + i) + (4 + 2 * i + n - i)
         else:
-            total += (6 + n - i) + (2 + 2 * (n - i) + i) + (2 + i) + (3 if one else 2 + n - i)
-    total += 6 + 2 + (5 + n) + (2 + 2 * n) + (3 if one else 2 + n)
+            total += (3 + n - i) + (2 + 2 * (n - i) + i) + (2 + i) + (3 if one else 2 + n - i)
+    total += 3 + 2 + (5 + 2 * n) + (2 + 2 * n) + (3 if one else 2 + n)
     return total / n
 
 

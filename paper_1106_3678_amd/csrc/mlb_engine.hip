@@ -480,6 +480,8 @@ __global__ void k_init_state(State<Sc>* st, double tol, long long maxit, double 
   for (int q = 0; q < NMAX; ++q) st->c[q] = st->cinv[q] = st->t[q] = st->tg[q] = st->beta[q] = zero<Sc>();
   for (int q = 0; q < NMAX * NMAX; ++q) st->S[q] = zero<Sc>();
   for (int q = 0; q < 8; ++q) st->aux[q] = zero<Sc>();
+  for (int q = 0; q < NMAX; ++q) st->alph[q] = zero<Sc>();
+  st->npend = 0;
   st->host_done = host_done;
   st->best_err = 0.0;
   st->best_k = 0;
@@ -761,9 +763,15 @@ struct Engine {
     const Timed tm = timed(MLB_KERNEL_ALPHA_STEP);
     // inner steps of the Gram form: also the S column of w = w_{i-1} (PH_INNER_S)
     const bool sw = s_alpha && phase == PH_INNER;
-#define MLB_ALPHA(B, SW)                                                                                      \
-  MLB_LAUNCH((k_alpha<V, Sc, B, SW>), SW ? grid_sw : grid_vec, s, tm, st, part, N, x, gh, r, w, Q, ldq, d0, nd, xrec, K, phase, i, j, \
-             n, flags)
+    // without an iterate record the x update is deferred to k_omega / k_xflush
+#define MLB_ALPHA2(B, SW, XD)                                                                                   \
+  MLB_LAUNCH((k_alpha<V, Sc, B, SW, XD>), SW ? grid_sw : grid_vec, s, tm, st, part, N, x, gh, r, w, Q, ldq, d0, nd, xrec, \
+             K, phase, i, j, n, flags)
+#define MLB_ALPHA(B, SW)              \
+  do {                                \
+    if (xrec) MLB_ALPHA2(B, SW, false); \
+    else MLB_ALPHA2(B, SW, true);       \
+  } while (0)
     if (sw) {
       switch (nb) {
         case 4: MLB_ALPHA(4, true); break;
@@ -779,6 +787,7 @@ struct Engine {
       }
     }
 #undef MLB_ALPHA
+#undef MLB_ALPHA2
     if (!(flags & F_SKIP_SCALAR)) {
       if (sw) scalar(grid_sw, 2 * nb + 1, 1 + nb + nd, PH_INNER_S, i, j);
       else scalar(grid_vec, nb + 1, nd + 1, phase, i, j);
@@ -832,8 +841,15 @@ struct Engine {
   }
   void omega_update(V* x, V* xrec, long long K) {
     const int nq = literal ? 1 : n;   // the literal order needs only e = q_1^H r here
-#define MLB_OM(B) \
-  k_omega<V, Sc, B><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, r, z, Q, ldq, nq, xrec, K, PH_OMEGA_UPD, n, force_flags)
+#define MLB_OM(B)                                                                                              \
+  do {                                                                                                        \
+    if (xrec)                                                                                                 \
+      k_omega<V, Sc, B, false><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, r, z, Q, ldq, nq, xrec, K, PH_OMEGA_UPD, n, \
+                                                          force_flags, (const V*)G, (long long)N);            \
+    else                                                                                                      \
+      k_omega<V, Sc, B, true><<<grid_vec, BLOCK, 0, s>>>(st, part, N, x, r, z, Q, ldq, nq, xrec, K, PH_OMEGA_UPD, n, \
+                                                         force_flags, (const V*)G, (long long)N);             \
+  } while (0)
     switch (nb) {
       case 4: MLB_OM(4); break;
       case 8: MLB_OM(8); break;
@@ -942,6 +958,8 @@ struct Engine {
         if (*(volatile int*)host_done) break;
       }
     }
+    // the alpha steps still pending when the solve ended within a cycle
+    if (!xrec) k_xflush<V, Sc><<<grid_vec, BLOCK, 0, s>>>(st, N, x, (const V*)G, (long long)N);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     Out o{};
@@ -982,6 +1000,8 @@ struct Engine {
         if (d) break;
       }
     }
+    // the alpha steps still pending when the solve ended within a cycle
+    if (!xrec) k_xflush<V, Sc><<<grid_vec, BLOCK, 0, s>>>(st, N, x, (const V*)G, (long long)N);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     State<Sc> h;

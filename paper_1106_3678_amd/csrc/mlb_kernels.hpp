@@ -110,6 +110,12 @@ struct State {
   long long best_k;     // iteration at which best_err last halved
   long long stag_window;  // > 0: stop with flag 2 after this many iterations without halving
   int* host_done;       // host-mapped copy of `done` (may be null)
+  // Deferred x updates (solves that record no iterates): alph[t] is the alpha that
+  // multiplies g in column t of G this cycle (set with it by the SpMV step of
+  // column t); npend of them are pending: x_k = x + sum_{t < npend} alph[t] G_t.
+  Sc alph[NMAX];
+  int npend;
+  int npad_;
   Sc S[NMAX * NMAX];    // S[s * NMAX + u] = q_s^H w_u  (s >= u); last, so rows s >= n can be left out of copies
 };
 
@@ -259,6 +265,7 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
         st->best_k = 0;
         st->iter = 0;
         st->e = sums[2];
+        st->npend = 0;
       }
       if (!finite(err)) finish(st, -1);
       else if (err < st->tol) finish(st, 0);
@@ -276,6 +283,7 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (w0) {
         st->iter = k;
         st->err = err;
+        st->npend = i;                       // x_{jn+i} = x + sum_{t < i} alph[t] G_t
       }
       if (!finite(err)) { finish(st, -1); break; }
       if (err < st->tol) { finish(st, 0); break; }
@@ -291,6 +299,7 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (w0) {
         st->uu = uu;
         st->err = err;
+        st->npend = n;                       // the half-step x: all n alpha steps of the cycle
       }
       if (!finite(err)) { finish(st, -1); break; }
       if (err < st->tol) {
@@ -316,6 +325,7 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (w0) {
         st->cinv[i] = sc_div(from_real<Sc>(1.0), ci);
         st->alpha = sc_div(st->e, ci);
+        st->alph[i] = st->alpha;             // multiplies G_i in the next alpha step
       }
       break;
     }
@@ -346,6 +356,7 @@ __device__ void scalar_program(State<Sc>* st, const Sc* sums, int phase, int i, 
       if (w0) {
         st->iter = k;
         st->err = err;
+        st->npend = 0;                       // k_omega applied the cycle's alpha steps
       }
       if (!finite(err)) { finish(st, -1); break; }
       if (err < st->tol) { finish(st, 0); break; }
@@ -485,11 +496,13 @@ __global__ __launch_bounds__((sblock<Sc, STRIDE>())) void k_scalar(State<Sc>* st
 // SW: also q_s^H w for the same s (the S column of w below its diagonal), at
 // sums[1 + ND + d]; the partial rows are then 2 ND + 1 long.
 // With xrec, x_k is also stored in column k-1 of the iterate record.
+// XD: x is not touched (neither x nor gh is read): the update is deferred to
+// k_omega, or to k_xflush when the solve ends within the cycle.
 // All ND column loads of a row are issued together, before any is used: the
 // columns past nd repeat column d0 (cache hits) and feed sums that no
 // recurrence reads.  Loads under a per-column test are issued one at a time,
 // each waited for (2-4% slower solves at n = 8, 16).  k_omega does the same.
-template <class V, class Sc, int ND, bool SW>
+template <class V, class Sc, int ND, bool SW, bool XD>
 __global__ __launch_bounds__(BLOCK) void k_alpha(State<Sc>* st, Sc* partial, int N, V* __restrict__ x,
                                                  const V* __restrict__ gh, V* __restrict__ r, const V* __restrict__ w,
                                                  const V* __restrict__ Q, long long ldq, int d0, int nd,
@@ -505,15 +518,22 @@ __global__ __launch_bounds__(BLOCK) void k_alpha(State<Sc>* st, Sc* partial, int
   const long long k = st->iter + 1;
   V* rec = (xrec && k <= K) ? xrec + (k - 1) * (long long)N : nullptr;
   for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
-    const V gv = gh[row], wv = w[row], x0 = x[row], r0 = r[row];
+    const V wv = w[row], r0 = r[row];
+    V gv = zero<V>(), x0 = zero<V>();
+    if constexpr (!XD) {
+      gv = gh[row];
+      x0 = x[row];
+    }
     V qv[ND];
     if (nd > 0) {
 #pragma unroll
       for (int d = 0; d < ND; ++d) qv[d] = Q[row + (long long)(d0 + (d < nd ? d : 0)) * ldq];
     }
-    V xv = axpy(x0, al, gv);
-    x[row] = xv;
-    if (rec) rec[row] = xv;
+    if constexpr (!XD) {
+      V xv = axpy(x0, al, gv);
+      x[row] = xv;
+      if (rec) rec[row] = xv;
+    }
     V rv = axpy(r0, mal, wv);
     r[row] = rv;
     cdot_acc(acc[0], rv, rv);
@@ -713,11 +733,14 @@ __global__ __launch_bounds__(BLOCK) void k_lit_beta(State<Sc>* st, Sc* partial, 
 }
 
 // x += omega u ; r = u - omega z (u held in r) ; sums: ||r||^2, q_s^H r, s < nd.
-template <class V, class Sc, int ND>
+// XD: first the cycle's deferred alpha steps, x += alph[t] G_t for t < npend in
+// order (the same fused multiply-adds, in the same order, as the alpha passes
+// would have made), then the omega step.
+template <class V, class Sc, int ND, bool XD>
 __global__ __launch_bounds__(BLOCK) void k_omega(State<Sc>* st, Sc* partial, int N, V* __restrict__ x,
                                                  V* __restrict__ r, const V* __restrict__ z, const V* __restrict__ Q,
                                                  long long ldq, int nd, V* __restrict__ xrec, long long K, int phase,
-                                                 int n, int flags) {
+                                                 int n, int flags, const V* __restrict__ G, long long ldg) {
   if (!(flags & F_IGNORE_DONE) && st->done) return;
   V acc[ND + 1];
 #pragma unroll
@@ -726,12 +749,30 @@ __global__ __launch_bounds__(BLOCK) void k_omega(State<Sc>* st, Sc* partial, int
   const V mom = convert<V>(zero<Sc>() - st->omega);
   const long long k = st->iter + 1;
   V* rec = (xrec && k <= K) ? xrec + (k - 1) * (long long)N : nullptr;
+  __shared__ V ca[NMAX];
+  int np = 0;
+  if constexpr (XD) {
+    np = st->npend;
+    if (threadIdx.x < np) ca[threadIdx.x] = convert<V>(st->alph[threadIdx.x]);
+    __syncthreads();
+  }
   for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
     const V u = r[row], x0 = x[row], zv = z[row];
     V qv[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) qv[d] = Q[row + (long long)(d < nd ? d : 0) * ldq];
-    V xv = axpy(x0, om, u);
+    V xa = x0;
+    if constexpr (XD) {
+      for (int t4 = 0; t4 < np; t4 += 4) {   // columns in groups of 4, loads issued together
+        V gv[4];
+#pragma unroll
+        for (int u4 = 0; u4 < 4; ++u4) gv[u4] = G[row + (long long)(t4 + u4 < np ? t4 + u4 : np - 1) * ldg];
+#pragma unroll
+        for (int u4 = 0; u4 < 4; ++u4)
+          if (t4 + u4 < np) xa = axpy(xa, ca[t4 + u4], gv[u4]);
+      }
+    }
+    V xv = axpy(xa, om, u);
     x[row] = xv;
     if (rec) rec[row] = xv;
     V rv = axpy(u, mom, zv);
@@ -742,6 +783,24 @@ __global__ __launch_bounds__(BLOCK) void k_omega(State<Sc>* st, Sc* partial, int
   }
   if (flags & F_SKIP_SCALAR) return;
   block_partials<ND + 1>(acc, nd + 1, partial);
+}
+
+// The deferred alpha steps of a solve that ended within a cycle:
+// x += alph[t] G_t for t < npend, in order (nothing when npend is 0).  Runs
+// after the done flag is set, so it does not test it.
+template <class V, class Sc>
+__global__ __launch_bounds__(BLOCK) void k_xflush(const State<Sc>* st, int N, V* __restrict__ x,
+                                                  const V* __restrict__ G, long long ldg) {
+  const int np = st->npend;
+  if (np == 0) return;
+  __shared__ V ca[NMAX];
+  if (threadIdx.x < np) ca[threadIdx.x] = convert<V>(st->alph[threadIdx.x]);
+  __syncthreads();
+  for (int row = blockIdx.x * BLOCK + threadIdx.x; row < N; row += gridDim.x * BLOCK) {
+    V xa = x[row];
+    for (int t = 0; t < np; ++t) xa = axpy(xa, ca[t], G[row + (long long)t * ldg]);
+    x[row] = xa;
+  }
 }
 
 // ---------------------------------------------------------------- small helpers

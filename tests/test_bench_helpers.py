@@ -76,18 +76,21 @@ def test_cpu_baseline_sample_is_bounded():
 
 
 def test_vector_passes_by_hand():
-    """n = 2: inner step i = 1 moves (6 + 1) + (2 + 2 + 1) + (2 + 1) + (2 + 1) = 18 vectors, the cycle end
-    6 + 2 + 7 + 6 + 4 = 25; 43 per cycle of 2 iterations.  n = 1 (BiCGStab): 21 per iteration.
-    n = 8 (S column from the alpha pass, every SpMV step 3 vectors): inner steps
-    (14 - i) + (18 - i) + (2 + i) + 3 = 37 - i, i = 1..7: 231; cycle end 6 + 2 + 13 + 18 + 3 = 42;
-    273 per cycle, n(n - 1)/2 = 28 fewer than with the S column in the SpMV epilogue."""
-    assert bench.vector_passes_per_iter(2) == 43 / 2
-    assert bench.vector_passes_per_iter(1) == 21
-    assert bench.vector_passes_per_iter(8) == 273 / 8
-    assert bench.vector_passes_per_iter(8, sv=16) == 273 / 8
+    """x updates deferred to the omega pass (no iterate record).  n = 2: inner step i = 1 moves
+    (3 + 1) + (2 + 2 + 1) + (2 + 1) + (2 + 1) = 15 vectors, the cycle end 3 + 2 + 9 + 6 + 4 = 24;
+    39 per cycle of 2 iterations.  n = 1 (BiCGStab): 3 + 2 + 7 + 4 + 3 = 19 per iteration.  n = 4:
+    inner steps 25 - 2i (23 + 21 + 19), cycle end 3 + 2 + 13 + 10 + 6 = 34; 97 per cycle.  n = 8 (S
+    column from the alpha pass, every SpMV step 3 vectors): inner steps (11 - i) + (18 - i) + (2 + i) + 3
+    = 34 - i, i = 1..7: 210; cycle end 3 + 2 + 21 + 18 + 3 = 47; 257 per cycle, n(n - 1)/2 = 28 fewer
+    than with the S column in the SpMV epilogue."""
+    assert bench.vector_passes_per_iter(2) == 39 / 2
+    assert bench.vector_passes_per_iter(1) == 19
+    assert bench.vector_passes_per_iter(4) == 97 / 4
+    assert bench.vector_passes_per_iter(8) == 257 / 8
+    assert bench.vector_passes_per_iter(8, sv=16) == 257 / 8
     assert bench.vector_passes_per_iter(16, sv=16) * 16 - bench.vector_passes_per_iter(16) * 16 == 16 * 15 / 2
-    # transpose-free, n = 2: (6 + 1) + (2 + 2) + (2 + 1) + (4 + 2 + 1) = 21 per inner step
-    assert bench.vector_passes_per_iter(2, transpose_free=True) == (21 + 25) / 2
+    # transpose-free, n = 2: (3 + 1) + (2 + 2) + (2 + 1) + (4 + 2 + 1) = 18 per inner step
+    assert bench.vector_passes_per_iter(2, transpose_free=True) == (18 + 24) / 2
 
 
 def test_spmv_step_bytes_literal_order():
