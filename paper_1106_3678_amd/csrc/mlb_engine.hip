@@ -244,7 +244,8 @@ struct IluFactor {
   int* dposH = nullptr;
   V* dinv = nullptr;                  // inverse diagonal (blocks) of F (U_ii^{-1}) and FH ((U_ii^H)^{-1})
   V* dinvH = nullptr;
-  int *ordL = nullptr, *ordU = nullptr, *ordHf = nullptr, *ordHb = nullptr;   // rows by level (device)
+  int* ordL = nullptr;                                                         // rows by level of L (device)
+  int4 *lvL = nullptr, *lvU = nullptr, *lvHf = nullptr, *lvHb = nullptr;       // the solves' rows and ranges
   std::vector<int> ptrL, ptrU, ptrHf, ptrHb;                                   // level pointers (host)
   V* tmid = nullptr;                  // intermediate vector of the two solves
 };
@@ -252,25 +253,44 @@ struct IluFactor {
 static int level_grid(int count) { return std::max(1, std::min((count + BLOCK - 1) / BLOCK, 4096)); }
 
 template <class V, int BS, bool LOWER, bool UNIT>
-static void ilu_sweep(const Mat<V>& M, const int* dpos, const V* dinv, const int* ord, const std::vector<int>& ptr,
-                      const V* in, V* out, hipStream_t s, const int* done) {
+static void ilu_sweep(const Mat<V>& M, const V* dinv, const int4* lv, const std::vector<int>& ptr, const V* in,
+                      V* out, hipStream_t s, const int* done) {
   const int nlev = (int)ptr.size() - 1;
   for (int t = 0; t < nlev; ++t) {
     const int c = ptr[t + 1] - ptr[t];   // levels in the order they are solved
-    k_ilu_solve_level<V, BS, LOWER, UNIT><<<level_grid(c), BLOCK, 0, s>>>(M.rp, M.ci, M.val, dpos, dinv,
-                                                                          ord + ptr[t], c, in, out, done);
+    k_ilu_solve_level<V, BS, LOWER, UNIT><<<level_grid(c), BLOCK, 0, s>>>(M.ci, M.val, dinv, lv + ptr[t], c, in,
+                                                                          out, done);
   }
+}
+
+// The rows of a sweep in solve order with their entry ranges (host): {i, q0, q1, 0},
+// [q0, q1) the stored entries left (lower) or right of row i's diagonal.  Every row
+// has a stored diagonal (checked before).
+static std::vector<int4> level_rows(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& ord,
+                                    bool lower) {
+  std::vector<int4> out(ord.size());
+  for (size_t t = 0; t < ord.size(); ++t) {
+    const int i = ord[t];
+    int qd = rp[i];
+    for (int q = rp[i]; q < rp[i + 1]; ++q)
+      if (ci[q] == i) {
+        qd = q;
+        break;
+      }
+    out[t] = make_int4(i, lower ? rp[i] : qd + 1, lower ? qd : rp[i + 1], 0);
+  }
+  return out;
 }
 
 // out = M^{-1} in = U^{-1} (L^{-1} in) (in, out distinct from f.tmid and from each other).
 template <class V>
 static void ilu_apply(const IluFactor<V>& f, const V* in, V* out, hipStream_t s, const int* done) {
   if (f.bs == 1) {
-    ilu_sweep<V, 1, true, true>(f.F, f.dpos, f.dinv, f.ordL, f.ptrL, in, f.tmid, s, done);
-    ilu_sweep<V, 1, false, false>(f.F, f.dpos, f.dinv, f.ordU, f.ptrU, f.tmid, out, s, done);
+    ilu_sweep<V, 1, true, true>(f.F, f.dinv, f.lvL, f.ptrL, in, f.tmid, s, done);
+    ilu_sweep<V, 1, false, false>(f.F, f.dinv, f.lvU, f.ptrU, f.tmid, out, s, done);
   } else {
-    ilu_sweep<V, 3, true, true>(f.F, f.dpos, f.dinv, f.ordL, f.ptrL, in, f.tmid, s, done);
-    ilu_sweep<V, 3, false, false>(f.F, f.dpos, f.dinv, f.ordU, f.ptrU, f.tmid, out, s, done);
+    ilu_sweep<V, 3, true, true>(f.F, f.dinv, f.lvL, f.ptrL, in, f.tmid, s, done);
+    ilu_sweep<V, 3, false, false>(f.F, f.dinv, f.lvU, f.ptrU, f.tmid, out, s, done);
   }
 }
 
@@ -278,11 +298,11 @@ static void ilu_apply(const IluFactor<V>& f, const V* in, V* out, hipStream_t s,
 template <class V>
 static void ilu_apply_h(const IluFactor<V>& f, V* v, hipStream_t s, const int* done) {
   if (f.bs == 1) {
-    ilu_sweep<V, 1, true, false>(f.FH, f.dposH, f.dinvH, f.ordHf, f.ptrHf, v, f.tmid, s, done);
-    ilu_sweep<V, 1, false, true>(f.FH, f.dposH, f.dinvH, f.ordHb, f.ptrHb, f.tmid, v, s, done);
+    ilu_sweep<V, 1, true, false>(f.FH, f.dinvH, f.lvHf, f.ptrHf, v, f.tmid, s, done);
+    ilu_sweep<V, 1, false, true>(f.FH, f.dinvH, f.lvHb, f.ptrHb, f.tmid, v, s, done);
   } else {
-    ilu_sweep<V, 3, true, false>(f.FH, f.dposH, f.dinvH, f.ordHf, f.ptrHf, v, f.tmid, s, done);
-    ilu_sweep<V, 3, false, true>(f.FH, f.dposH, f.dinvH, f.ordHb, f.ptrHb, f.tmid, v, s, done);
+    ilu_sweep<V, 3, true, false>(f.FH, f.dinvH, f.lvHf, f.ptrHf, v, f.tmid, s, done);
+    ilu_sweep<V, 3, false, true>(f.FH, f.dinvH, f.lvHb, f.ptrHb, f.tmid, v, s, done);
   }
 }
 
@@ -350,8 +370,11 @@ static void build_ilu(const Mat<V>& A, IluFactor<V>& f, Allocs& al, hipStream_t 
   HIP_TRY(hipMemcpyAsync(f.ordL, ord.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
   std::vector<int> ordU;
   level_sets(hrp, hci, false, ordU, f.ptrU);
-  f.ordU = al.get<int>(m);
-  HIP_TRY(hipMemcpyAsync(f.ordU, ordU.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  const std::vector<int4> lvL = level_rows(hrp, hci, ord, true), lvU = level_rows(hrp, hci, ordU, false);
+  f.lvL = al.get<int4>(m);
+  f.lvU = al.get<int4>(m);
+  HIP_TRY(hipMemcpyAsync(f.lvL, lvL.data(), sizeof(int4) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(f.lvU, lvU.data(), sizeof(int4) * m, hipMemcpyHostToDevice, s));
   // factorisation, one launch per level of L
   for (size_t l = 0; l + 1 < f.ptrL.size(); ++l) {
     const int c = f.ptrL[l + 1] - f.ptrL[l];
@@ -377,18 +400,19 @@ static void build_ilu(const Mat<V>& A, IluFactor<V>& f, Allocs& al, hipStream_t 
   std::vector<int> ordHf, ordHb;
   level_sets(hrpH, hciH, true, ordHf, f.ptrHf);
   level_sets(hrpH, hciH, false, ordHb, f.ptrHb);
-  f.ordHf = al.get<int>(m);
-  f.ordHb = al.get<int>(m);
-  HIP_TRY(hipMemcpyAsync(f.ordHf, ordHf.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(f.ordHb, ordHb.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+  const std::vector<int4> lvHf = level_rows(hrpH, hciH, ordHf, true), lvHb = level_rows(hrpH, hciH, ordHb, false);
+  f.lvHf = al.get<int4>(m);
+  f.lvHb = al.get<int4>(m);
+  HIP_TRY(hipMemcpyAsync(f.lvHf, lvHf.data(), sizeof(int4) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(f.lvHb, lvHb.data(), sizeof(int4) * m, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));   // the host vectors above are copied before they go
 }
 
 // Device bytes build_ilu allocates (beside the transpose's own temporaries).
 static size_t ilu_bytes(long long nnz, int m, int bs, size_t sv) {
   const size_t b2 = (size_t)bs * bs;
-  return (size_t)nnz * 4 * 2 + (size_t)nnz * b2 * sv * 2 + (size_t)(m + 1) * 4 + (size_t)m * 4 * 6 +
-         (size_t)m * b2 * sv * 2 + (size_t)m * bs * sv;
+  return (size_t)nnz * 4 * 2 + (size_t)nnz * b2 * sv * 2 + (size_t)(m + 1) * 4 + (size_t)m * 4 * 3 +
+         (size_t)m * sizeof(int4) * 4 + (size_t)m * b2 * sv * 2 + (size_t)m * bs * sv;
 }
 
 // ------------------------------------------------------------------ launch dispatch

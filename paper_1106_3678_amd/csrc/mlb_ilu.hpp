@@ -131,42 +131,60 @@ __global__ void k_ilu_inv_diag(const V* __restrict__ val, const int* __restrict_
   }
 }
 
-// One level of a triangular solve with a factor matrix (rows sorted, dpos the
-// diagonal).  LOWER: out_i = in_i - sum_{stored j < i} a_ij out_j; else
-// out_i = in_i - sum_{stored j > i} a_ij out_j.  UNIT: that value is out_i;
-// else out_i = a_ii^{-1} (value): a division for scalars, the stored inverse
-// block (dinv) for 3x3 blocks.  The rows of a level only read out_j of earlier
-// levels.  in and out are BS-vectors per (block) row; they may not overlap.
-// done: the solve's done flag (the launch returns at once when it is set), or
-// null outside an iteration.
+// One level of a triangular solve with a factor matrix (rows sorted).  LOWER:
+// out_i = in_i - sum_{stored j < i} a_ij out_j; else out_i = in_i -
+// sum_{stored j > i} a_ij out_j.  UNIT: that value is out_i; else out_i =
+// a_ii^{-1} (value): a division for scalars, the stored inverse block (dinv)
+// for 3x3 blocks.  The rows of a level only read out_j of earlier levels.  in
+// and out are BS-vectors per (block) row; they may not overlap.  lv: the
+// level's rows in solve order, {i, q0, q1, 0} with [q0, q1) the stored entries
+// left (LOWER) or right of row i's diagonal, so one load gives a row and its
+// range (the diagonal entry is q1, or q0 - 1).  done: the solve's done flag
+// (the launch returns at once when it is set), or null outside an iteration.
 template <class V, int BS, bool LOWER, bool UNIT>
-__global__ void k_ilu_solve_level(const int* __restrict__ rp, const int* __restrict__ ci, const V* __restrict__ val,
-                                  const int* __restrict__ dpos, const V* __restrict__ dinv,
-                                  const int* __restrict__ rows, int count, const V* __restrict__ in,
-                                  V* __restrict__ out, const int* done) {
+__global__ void k_ilu_solve_level(const int* __restrict__ ci, const V* __restrict__ val,
+                                  const V* __restrict__ dinv, const int4* __restrict__ lv, int count,
+                                  const V* __restrict__ in, V* __restrict__ out, const int* done) {
   constexpr int B2 = BS * BS;
+  const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  int4 rnext = t0 < count ? lv[t0] : make_int4(0, 0, 0, 0);   // issued before the flag test
   if (done && *(volatile const int*)done) return;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-    const int i = rows[t];
-    const int qd = dpos[i];
-    const int q0 = LOWER ? rp[i] : qd + 1;
-    const int q1 = LOWER ? qd : rp[i + 1];
+  for (int t = t0; t < count; t += stride) {
+    const int4 rw = rnext;
+    if (t + stride < count) rnext = lv[t + stride];
+    const int i = rw.x, q0 = rw.y, q1 = rw.z;
+    const int qd = LOWER ? q1 : q0 - 1;
     V s[BS];
 #pragma unroll
     for (int e = 0; e < BS; ++e) s[e] = in[(size_t)BS * i + e];
-    for (int q = q0; q < q1; ++q) {
-      const V* a = val + (size_t)B2 * q;
-      const V* xo = out + (size_t)BS * ci[q];
-      V xv[BS];
+    // entries in groups of 4: their indices and values loaded together, then the solved
+    // values they reference, then the updates in entry order (past q1: entry q1 - 1 again,
+    // unused)
+    for (int q4 = q0; q4 < q1; q4 += 4) {
+      int c[4];
+      V a[4][B2], xv[4][BS];
 #pragma unroll
-      for (int e = 0; e < BS; ++e) xv[e] = xo[e];
+      for (int u = 0; u < 4; ++u) {
+        const int q = q4 + u < q1 ? q4 + u : q1 - 1;
+        c[u] = ci[q];
 #pragma unroll
-      for (int r = 0; r < BS; ++r) {
-        V acc = zero<V>();
-#pragma unroll
-        for (int k = 0; k < BS; ++k) acc = axpy(acc, a[BS * r + k], xv[k]);
-        s[r] = s[r] - acc;
+        for (int e = 0; e < B2; ++e) a[u][e] = val[(size_t)B2 * q + e];
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < BS; ++e) xv[u][e] = out[(size_t)BS * c[u] + e];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q4 + u < q1) {
+#pragma unroll
+          for (int r = 0; r < BS; ++r) {
+            V acc = zero<V>();
+#pragma unroll
+            for (int k = 0; k < BS; ++k) acc = axpy(acc, a[u][BS * r + k], xv[u][k]);
+            s[r] = s[r] - acc;
+          }
+        }
     }
     if constexpr (UNIT) {
 #pragma unroll
