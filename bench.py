@@ -444,7 +444,7 @@ def bench_sequence(args, torch, workloads, binding):
         seq.solve(rhs[0], x, Qv)   # warm-up (first-use costs), not counted
         seq.close()
         seq = binding.Sequence(dA, n0, lo, hi, step, tol=p.tol, maxit=p.maxit, precond=pre)
-        total, used, iters, errs = 0.0, [], [], []
+        total, used, iters, errs, flags = 0.0, [], [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for b in rhs:
@@ -454,11 +454,12 @@ def bench_sequence(args, torch, workloads, binding):
             used.append(n)
             iters.append(int(res.iter))
             errs.append(res.err_true)
+            flags.append(int(res.flag))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         seq.close()
-        out[var] = {"solve_ms_total": total, "wall_s": wall, "n_used": used, "iterations": iters,
-                    "max_err_true": max(errs)}
+        out[var] = {"solve_ms_total": total, "wall_s": wall, "n_used": used, "iterations": iters, "flags": flags,
+                    "err_true": errs, "max_err_true": max(errs)}
         log(f"[bench] sequence {var}: {total:.1f} ms over {len(rhs)} systems, n {used}, iterations {iters}")
     base = out["bicgstab_n1"]["solve_ms_total"]
     best = min(v["solve_ms_total"] for k, v in out.items() if k != "bicgstab_n1")

@@ -252,7 +252,10 @@ int mlbicgstab_destroy(mlb_handle h);
  * y = A x (op = MLB_OP_A, the caller's A) or y = A^H x (op = MLB_OP_AH, the
  * conjugate transpose the solver built for f_s = A^H q_s, Algorithm 4.1 step
  * 2).  A transpose_free or preconditioned solver holds no A^H of A:
- * MLB_OP_AH returns MLB_EUNSUPPORTED there.  x and y are device vectors of N
+ * MLB_OP_AH returns MLB_EUNSUPPORTED there.  With an ILU(0) preconditioner
+ * (the M of Algorithm 7.1) also y = M^{-1} x (MLB_OP_MINV) and y = M^{-H} x
+ * (MLB_OP_MINVH), the two triangular solves each application runs; other
+ * solvers return MLB_EUNSUPPORTED for them.  x and y are device vectors of N
  * values of the solver's value type (x is read, y written; they must not
  * overlap; both are borrowed for the call).  Runs the library's SpMV kernel on
  * the solver's stream and synchronises it; it reads and writes no solver state,
@@ -260,7 +263,7 @@ int mlbicgstab_destroy(mlb_handle h);
  * of the products.  Returns 0; MLB_EINVAL for a NULL handle, x or y or an
  * unknown op; MLB_EUNSUPPORTED as above; MLB_EHIP if the launch fails.
  */
-enum { MLB_OP_A = 0, MLB_OP_AH = 1 };
+enum { MLB_OP_A = 0, MLB_OP_AH = 1, MLB_OP_MINV = 2, MLB_OP_MINVH = 3 };
 int mlbicgstab_matvec(mlb_handle h, int32_t op, const void* x, void* y);
 
 /*

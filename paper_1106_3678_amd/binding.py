@@ -20,7 +20,7 @@ MLB_CSR, MLB_BSR3 = 0, 1
 MLB_PREC_FP64, MLB_PREC_FP32_IR = 0, 1
 MLB_PRECOND_NONE, MLB_PRECOND_JACOBI, MLB_PRECOND_ILU0 = 0, 1, 2
 MLB_ORDER_FUSED, MLB_ORDER_LITERAL = 0, 1
-MLB_OP_A, MLB_OP_AH = 0, 1
+MLB_OP_A, MLB_OP_AH, MLB_OP_MINV, MLB_OP_MINVH = 0, 1, 2, 3
 MLB_MAX_N = 32
 MLB_MAX_INDEX = 2 ** 31 - 2 ** 20   # largest nrows and nnz
 MLB_KERNEL_SPMV_STEP, MLB_KERNEL_ALPHA_STEP, MLB_KERNEL_COMBINE, MLB_KERNEL_RECOMBINE = 0, 1, 2, 3
@@ -412,7 +412,8 @@ class Solver:
         return mlbicgstab_time_kernel(self.h, kernel, reps)
 
     def matvec(self, x, y, op: int = MLB_OP_A) -> None:
-        """y = A x (op = MLB_OP_A) or y = A^H x (op = MLB_OP_AH) on the library's SpMV kernels."""
+        """y = A x (op = MLB_OP_A) or y = A^H x (op = MLB_OP_AH) on the library's SpMV kernels; with an
+        ILU(0) preconditioner also y = M^{-1} x (MLB_OP_MINV) and y = M^{-H} x (MLB_OP_MINVH)."""
         N = self.dmat.nrows
         if x.numel() != N or y.numel() != N or not x.is_contiguous() or not y.is_contiguous():
             raise ValueError("x and y must be contiguous vectors of length N")

@@ -236,6 +236,16 @@ static void level_sets(const std::vector<int>& rp, const std::vector<int>& ci, b
 
 // The ILU(0) factor of A, its conjugate transpose and the level sets of the
 // four triangular solves (L, U of the factor; U^H, L^H of its transpose).
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess || cus <= 0) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  return cus;
+}
+
 template <class V>
 struct IluFactor {
   int bs = 1, nbrows = 0;
@@ -246,22 +256,18 @@ struct IluFactor {
   V* dinvH = nullptr;
   int* ordL = nullptr;                                                         // rows by level of L (device)
   int4 *lvL = nullptr, *lvU = nullptr, *lvHf = nullptr, *lvHb = nullptr;       // the solves' rows and ranges
-  std::vector<int> ptrL, ptrU, ptrHf, ptrHb;                                   // level pointers (host)
+  std::vector<int> ptrL;                                                       // level pointers of L (host)
   V* tmid = nullptr;                  // intermediate vector of the two solves
+  unsigned* ctl = nullptr;            // one-launch solves: claim counters [0] and [1], lost-wait flag [2]
+  int sweep_grid = 1;                 // their workgroups (persistent: each wave claims until none are left)
 };
 
-static int level_grid(int count) { return std::max(1, std::min((count + BLOCK - 1) / BLOCK, 4096)); }
+// Waves of a one-launch triangular solve, as a multiple of the waves one
+// average level fills (capped at two per CU), one wave per workgroup so that
+// they spread over the CUs.
+static constexpr double ILU_SWEEP_LEVEL_MULT = 3.0;
 
-template <class V, int BS, bool LOWER, bool UNIT>
-static void ilu_sweep(const Mat<V>& M, const V* dinv, const int4* lv, const std::vector<int>& ptr, const V* in,
-                      V* out, hipStream_t s, const int* done) {
-  const int nlev = (int)ptr.size() - 1;
-  for (int t = 0; t < nlev; ++t) {
-    const int c = ptr[t + 1] - ptr[t];   // levels in the order they are solved
-    k_ilu_solve_level<V, BS, LOWER, UNIT><<<level_grid(c), BLOCK, 0, s>>>(M.ci, M.val, dinv, lv + ptr[t], c, in,
-                                                                          out, done);
-  }
-}
+static int level_grid(int count) { return std::max(1, std::min((count + BLOCK - 1) / BLOCK, 4096)); }
 
 // The rows of a sweep in solve order with their entry ranges (host): {i, q0, q1, 0},
 // [q0, q1) the stored entries left (lower) or right of row i's diagonal.  Every row
@@ -282,27 +288,52 @@ static std::vector<int4> level_rows(const std::vector<int>& rp, const std::vecto
   return out;
 }
 
-// out = M^{-1} in = U^{-1} (L^{-1} in) (in, out distinct from f.tmid and from each other).
+// One triangular solve in one launch (k_ilu_solve_sweep); `which` picks its claim counter.
+template <class V, int BS, bool LOWER, bool UNIT>
+static void ilu_sweep1(const IluFactor<V>& f, const Mat<V>& M, const V* dinv, const int4* lv, const V* in, V* out,
+                       V* next, int which, hipStream_t s, const int* done) {
+  k_ilu_solve_sweep<V, BS, LOWER, UNIT><<<f.sweep_grid, WAVE, 0, s>>>(M.ci, M.val, dinv, lv, f.nbrows, in, out,
+                                                                       next, f.ctl + which, f.ctl + 2, done);
+}
+
+// Marks f.tmid pending and resets both claim counters: the start of a pair of one-launch solves.
+template <class V>
+static void ilu_pending(const IluFactor<V>& f, hipStream_t s, const int* done) {
+  const long long nw = (long long)f.nbrows * f.bs * (long long)(sizeof(V) / 8);
+  k_ilu_pending<<<grid_for(nw, 4096), BLOCK, 0, s>>>(reinterpret_cast<unsigned long long*>(f.tmid), nw, f.ctl, done);
+}
+
+// out = M^{-1} in = U^{-1} (L^{-1} in) through f.tmid (out may be in).
 template <class V>
 static void ilu_apply(const IluFactor<V>& f, const V* in, V* out, hipStream_t s, const int* done) {
-  if (f.bs == 1) {
-    ilu_sweep<V, 1, true, true>(f.F, f.dinv, f.lvL, f.ptrL, in, f.tmid, s, done);
-    ilu_sweep<V, 1, false, false>(f.F, f.dinv, f.lvU, f.ptrU, f.tmid, out, s, done);
+  if constexpr (!std::is_same<typename traits<V>::real, double>::value) {
+    throw Error{MLB_EUNSUPPORTED, "ILU(0) runs on fp64 values only"};
   } else {
-    ilu_sweep<V, 3, true, true>(f.F, f.dinv, f.lvL, f.ptrL, in, f.tmid, s, done);
-    ilu_sweep<V, 3, false, false>(f.F, f.dinv, f.lvU, f.ptrU, f.tmid, out, s, done);
+    ilu_pending(f, s, done);
+    if (f.bs == 1) {
+      ilu_sweep1<V, 1, true, true>(f, f.F, f.dinv, f.lvL, in, f.tmid, out, 0, s, done);
+      ilu_sweep1<V, 1, false, false>(f, f.F, f.dinv, f.lvU, f.tmid, out, nullptr, 1, s, done);
+    } else {
+      ilu_sweep1<V, 3, true, true>(f, f.F, f.dinv, f.lvL, in, f.tmid, out, 0, s, done);
+      ilu_sweep1<V, 3, false, false>(f, f.F, f.dinv, f.lvU, f.tmid, out, nullptr, 1, s, done);
+    }
   }
 }
 
 // v = M^{-H} v = L^{-H} (U^{-H} v), in place through f.tmid.
 template <class V>
 static void ilu_apply_h(const IluFactor<V>& f, V* v, hipStream_t s, const int* done) {
-  if (f.bs == 1) {
-    ilu_sweep<V, 1, true, false>(f.FH, f.dinvH, f.lvHf, f.ptrHf, v, f.tmid, s, done);
-    ilu_sweep<V, 1, false, true>(f.FH, f.dinvH, f.lvHb, f.ptrHb, f.tmid, v, s, done);
+  if constexpr (!std::is_same<typename traits<V>::real, double>::value) {
+    throw Error{MLB_EUNSUPPORTED, "ILU(0) runs on fp64 values only"};
   } else {
-    ilu_sweep<V, 3, true, false>(f.FH, f.dinvH, f.lvHf, f.ptrHf, v, f.tmid, s, done);
-    ilu_sweep<V, 3, false, true>(f.FH, f.dinvH, f.lvHb, f.ptrHb, f.tmid, v, s, done);
+    ilu_pending(f, s, done);
+    if (f.bs == 1) {
+      ilu_sweep1<V, 1, true, false>(f, f.FH, f.dinvH, f.lvHf, v, f.tmid, v, 0, s, done);
+      ilu_sweep1<V, 1, false, true>(f, f.FH, f.dinvH, f.lvHb, f.tmid, v, nullptr, 1, s, done);
+    } else {
+      ilu_sweep1<V, 3, true, false>(f, f.FH, f.dinvH, f.lvHf, v, f.tmid, v, 0, s, done);
+      ilu_sweep1<V, 3, false, true>(f, f.FH, f.dinvH, f.lvHb, f.tmid, v, nullptr, 1, s, done);
+    }
   }
 }
 
@@ -351,6 +382,8 @@ static void build_ilu(const Mat<V>& A, IluFactor<V>& f, Allocs& al, hipStream_t 
   f.dpos = al.get<int>(m);
   f.dinv = al.get<V>((size_t)m * b2);
   f.tmid = al.get<V>((size_t)m * bs);
+  f.ctl = al.get<unsigned>(4);
+  k_fill<unsigned><<<1, BLOCK, 0, s>>>(f.ctl, 4, 0u);
   Allocs tmp_own(al.stream, al.ordered);
   int* bad = tmp_own.get<int>(1);
   k_fill<int><<<1, BLOCK, 0, s>>>(bad, 1, 0);
@@ -368,8 +401,12 @@ static void build_ilu(const Mat<V>& A, IluFactor<V>& f, Allocs& al, hipStream_t 
   level_sets(hrp, hci, true, ord, f.ptrL);
   f.ordL = al.get<int>(m);
   HIP_TRY(hipMemcpyAsync(f.ordL, ord.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
-  std::vector<int> ordU;
-  level_sets(hrp, hci, false, ordU, f.ptrU);
+  std::vector<int> ordU, ptrU;
+  level_sets(hrp, hci, false, ordU, ptrU);
+  {
+    const double level_waves = (double)m / (double)std::max<size_t>(1, f.ptrL.size() - 1) / WAVE;
+    f.sweep_grid = (int)std::min<double>(2.0 * device_cus(), std::max(1.0, ILU_SWEEP_LEVEL_MULT * level_waves));
+  }
   const std::vector<int4> lvL = level_rows(hrp, hci, ord, true), lvU = level_rows(hrp, hci, ordU, false);
   f.lvL = al.get<int4>(m);
   f.lvU = al.get<int4>(m);
@@ -397,9 +434,9 @@ static void build_ilu(const Mat<V>& A, IluFactor<V>& f, Allocs& al, hipStream_t 
   if (hb & 2) throw Error{MLB_EINVAL, "ILU(0): a zero or singular pivot"};
   const std::vector<int> hrpH = to_host(f.FH.rp, (size_t)m + 1, s);
   const std::vector<int> hciH = to_host(f.FH.ci, (size_t)A.nnz, s);
-  std::vector<int> ordHf, ordHb;
-  level_sets(hrpH, hciH, true, ordHf, f.ptrHf);
-  level_sets(hrpH, hciH, false, ordHb, f.ptrHb);
+  std::vector<int> ordHf, ordHb, ptrHf, ptrHb;
+  level_sets(hrpH, hciH, true, ordHf, ptrHf);
+  level_sets(hrpH, hciH, false, ordHb, ptrHb);
   const std::vector<int4> lvHf = level_rows(hrpH, hciH, ordHf, true), lvHb = level_rows(hrpH, hciH, ordHb, false);
   f.lvHf = al.get<int4>(m);
   f.lvHb = al.get<int4>(m);
@@ -412,7 +449,7 @@ static void build_ilu(const Mat<V>& A, IluFactor<V>& f, Allocs& al, hipStream_t 
 static size_t ilu_bytes(long long nnz, int m, int bs, size_t sv) {
   const size_t b2 = (size_t)bs * bs;
   return (size_t)nnz * 4 * 2 + (size_t)nnz * b2 * sv * 2 + (size_t)(m + 1) * 4 + (size_t)m * 4 * 3 +
-         (size_t)m * sizeof(int4) * 4 + (size_t)m * b2 * sv * 2 + (size_t)m * bs * sv;
+         (size_t)m * sizeof(int4) * 4 + (size_t)m * b2 * sv * 2 + (size_t)m * bs * sv + 16;
 }
 
 // ------------------------------------------------------------------ launch dispatch
@@ -474,16 +511,6 @@ static int launch_spmv_nd(const Mat<V>& A, int grid, hipStream_t s, State<Sc>* s
 #undef MLB_SPMV_CASE
 #undef MLB_SPMV_WCASE
   return 0;
-}
-
-static int device_cus() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                               hipSuccess || cus <= 0) {
-    (void)hipGetLastError();
-    cus = 256;
-  }
-  return cus;
 }
 
 // Resets the device scalars before a solve.
@@ -1286,6 +1313,20 @@ static bool debug_enabled() {
   return on;
 }
 
+// Throws when a one-launch triangular solve gave up a wait since the last check
+// (the flag is cleared first, so the factor stays usable).
+template <class V>
+static void ilu_check(const IluFactor<V>& f, hipStream_t s) {
+  unsigned e = 0;
+  HIP_TRY(hipMemcpyAsync(&e, f.ctl + 2, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (e) {
+    k_fill<unsigned><<<1, BLOCK, 0, s>>>(f.ctl + 2, 1, 0u);
+    HIP_TRY(hipStreamSynchronize(s));
+    throw Error{MLB_EHIP, "ILU(0): a triangular solve gave up waiting for a solved value"};
+  }
+}
+
 // x <- M x (forward) or x <- M^{-1} x (back) for `cols` columns; no-op without a preconditioner.
 template <class V64, class V32>
 static void precond_map(mlb_solver* h, Impl<V64, V32>& im, V64* x, int cols, long long ld, bool back) {
@@ -1316,6 +1357,7 @@ static typename Engine<V64>::Out fp64_iteration(mlb_solver* h, Impl<V64, V32>& i
   auto out = im.e64.solve(b, x, Q, ldq, o.tol, maxit, o.kappa, xrec, K);
   precond_map(h, im, x, 1, h->N, true);
   if (xrec) precond_map(h, im, xrec, (int)std::min<long long>(K, std::max<long long>(out.iter, 0)), h->N, true);
+  if (im.has_ilu) ilu_check(im.ilu, h->s);
   return out;
 }
 
@@ -1451,9 +1493,17 @@ static double time_kernel_impl(Engine<V>& e, int kernel, int reps) {
 // on the solver's stream (whatever the done flag of the last solve says).
 template <class V64, class V32>
 static void matvec_impl(mlb_solver* h, Impl<V64, V32>& im, int op, const V64* x, V64* y) {
-  im.e64.spmv_plain(op == MLB_OP_A ? im.A0 : im.e64.AH, x, y, F_IGNORE_DONE);
+  if (op == MLB_OP_MINV) {
+    ilu_apply(im.ilu, x, y, h->s, nullptr);
+  } else if (op == MLB_OP_MINVH) {
+    HIP_TRY(hipMemcpyAsync(y, x, sizeof(V64) * (size_t)h->N, hipMemcpyDeviceToDevice, h->s));
+    ilu_apply_h(im.ilu, y, h->s, nullptr);
+  } else {
+    im.e64.spmv_plain(op == MLB_OP_A ? im.A0 : im.e64.AH, x, y, F_IGNORE_DONE);
+  }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(h->s));
+  if (op == MLB_OP_MINV || op == MLB_OP_MINVH) ilu_check(im.ilu, h->s);
 }
 
 template <class F>
@@ -1829,9 +1879,11 @@ int mlb_sequence_destroy(mlb_sequence_handle q) {
 int mlbicgstab_matvec(mlb_handle h, int32_t op, const void* x, void* y) {
   return guarded([&]() -> int {
     if (!h || !x || !y) throw Error{MLB_EINVAL, "handle, x and y must be non-NULL"};
-    if (op != MLB_OP_A && op != MLB_OP_AH) throw Error{MLB_EINVAL, "op must be MLB_OP_A or MLB_OP_AH"};
+    if (op < MLB_OP_A || op > MLB_OP_MINVH) throw Error{MLB_EINVAL, "op must be MLB_OP_A, _AH, _MINV or _MINVH"};
     if (op == MLB_OP_AH && (h->opt.transpose_free || h->opt.precond != MLB_PRECOND_NONE))
       throw Error{MLB_EUNSUPPORTED, "A^H is held only without transpose_free and without a preconditioner"};
+    if ((op == MLB_OP_MINV || op == MLB_OP_MINVH) && h->opt.precond != MLB_PRECOND_ILU0)
+      throw Error{MLB_EUNSUPPORTED, "M^{-1} and M^{-H} are applied for an ILU(0) preconditioner only"};
     if (h->real)
       matvec_impl(h, *h->real, op, (const double*)x, (double*)y);
     else

@@ -5,7 +5,8 @@ Same bars as the other parity tests: flag, iteration count within 5%, x_1..x_20 
 residual below tol, x within 1e-6 -- strict everywhere except the ill-conditioned reservoir system,
 whose early iterates the oracle itself moves by up to 120% under a 1e-15 perturbation of b (there
 only the flag, the count, the residual and the final x are compared).  Also: a nonzero x_0 (the map y_0 = M x_0), the transpose-free and literal orders,
-the 128^3 benchmark operator with n = 4 against the oracle run to convergence, and the errors.
+the 128^3 benchmark operator with n = 4 against the oracle run to convergence, one application of
+M^{-1} and M^{-H} element by element (up to 128^3), and the errors.
 """
 import numpy as np
 import pytest
@@ -108,6 +109,50 @@ def test_full_size_convdiff3d_n4():
     configuration, against the oracle run to convergence."""
     p = workloads.config2(n=4, m=128)
     check_ilu(p)
+
+
+def _apply_both(p, seed=5):
+    """M^{-1} v and M^{-H} v from the library (mlbicgstab_matvec, ops MINV and MINVH: the one-launch
+    triangular solves of every application) and from the oracle's ILU(0), for one seeded v; also a
+    second MINV of the same v."""
+    cplx = np.iscomplexobj(p.A.data)
+    g = np.random.default_rng(seed)
+    v = g.standard_normal(p.N) + (1j * g.standard_normal(p.N) if cplx else 0.0)
+    s = binding.Solver(binding.to_device(p.A), p.n, tol=p.tol, maxit=p.maxit, precond=ILU)
+    try:
+        x = torch.from_numpy(np.ascontiguousarray(v)).cuda()
+        y, yh, y2 = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+        s.matvec(x, y, binding.MLB_OP_MINV)
+        s.matvec(x, yh, binding.MLB_OP_MINVH)
+        s.matvec(x, y2, binding.MLB_OP_MINV)
+        torch.cuda.synchronize()
+    finally:
+        s.close()
+    apply, apply_h = ilu0_precond(p.A)
+    return y.cpu().numpy(), yh.cpu().numpy(), y2.cpu().numpy(), apply(v), apply_h(v)
+
+
+@pytest.mark.parametrize("case", ["2d", "2d_ragged", "3d", "complex", "bsr3", "bsr3_larger", "full_128"])
+def test_apply_against_oracle(case):
+    """One application of M^{-1} and of M^{-H} element by element against the oracle's factor and
+    triangular solves.  Both sides form the same factor (the same products in the same order, up to
+    the fma contraction) and substitute in row order, so they differ by rounding only (6.4e-16 of the
+    largest entry at most in these cases); the bar is 1e-12 of it (the achieved value is printed).  A second application of the
+    same v is bitwise the first: each row's sum runs in entry order, whichever wave solves it and
+    whenever the values it reads arrive."""
+    p = {"2d": lambda: workloads.config1(n=4),
+         "2d_ragged": lambda: workloads.config1(n=4, m=33),
+         "3d": lambda: workloads.config2(n=4, m=20),
+         "complex": lambda: workloads.config5(n=4, m=12),
+         "bsr3": lambda: workloads.config3(n=4, grid=(8, 10, 6)),
+         "bsr3_larger": lambda: workloads.config3(n=4, grid=(20, 60, 30)),
+         "full_128": lambda: workloads.config2(n=4, m=128)}[case]()
+    y, yh, y2, yo, yho = _apply_both(p)
+    for name, a, ref in (("M^-1", y, yo), ("M^-H", yh, yho)):
+        err = np.max(np.abs(a - ref)) / np.max(np.abs(ref))
+        print(f"{case} {name}: max |gpu - oracle| / max |oracle| = {err:.2e} (bar 1e-12)")
+        assert np.all(np.isfinite(a)) and err <= 1e-12, (case, name, err)
+    assert np.array_equal(y, y2), case
 
 
 def _solver_error(A, opt_precond=ILU, precision=0):

@@ -149,8 +149,12 @@ def test_bad_op_and_shapes():
     try:
         x = torch.zeros(A.shape[0], dtype=torch.float64, device="cuda")
         with pytest.raises(binding.MlbError) as e:
-            s.matvec(x, torch.empty_like(x), 2)
+            s.matvec(x, torch.empty_like(x), 4)
         assert e.value.code == binding.MLB_EINVAL
+        for op in (binding.MLB_OP_MINV, binding.MLB_OP_MINVH):   # no ILU(0) preconditioner here
+            with pytest.raises(binding.MlbError) as e:
+                s.matvec(x, torch.empty_like(x), op)
+            assert e.value.code == binding.MLB_EUNSUPPORTED
         with pytest.raises(ValueError):
             s.matvec(x[:-1], torch.empty_like(x))
     finally:
