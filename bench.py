@@ -438,12 +438,14 @@ def bench_sequence(args, torch, workloads, binding):
     out = {}
     for var, n0, lo, hi, step in [("bicgstab_n1", 1, 1, 1, 0), ("fixed_n4", 4, 4, 4, 0), ("fixed_n8", 8, 8, 8, 0),
                                   ("auto_from_n4_step2", 4, 1, n_max, 2)]:
-        seq = binding.Sequence(dA, n0, lo, hi, step, tol=p.tol, maxit=p.maxit, precond=pre)
+        seq = binding.Sequence(dA, n0, lo, hi, step, tol=p.tol, maxit=p.maxit, precond=pre,
+                               max_restarts=args.max_restarts)
         Qv = Q[:, :hi]
         x.zero_()
         seq.solve(rhs[0], x, Qv)   # warm-up (first-use costs), not counted
         seq.close()
-        seq = binding.Sequence(dA, n0, lo, hi, step, tol=p.tol, maxit=p.maxit, precond=pre)
+        seq = binding.Sequence(dA, n0, lo, hi, step, tol=p.tol, maxit=p.maxit, precond=pre,
+                               max_restarts=args.max_restarts)
         total, used, iters, errs, flags = 0.0, [], [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -468,7 +470,7 @@ def bench_sequence(args, torch, workloads, binding):
         "unit": "s", "n_gpus": 1, "steps": len(rhs), "warmup": 1,
         "ms_per_step": 1e3 * out["auto_from_n4_step2"]["wall_s"] / len(rhs), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": name, "N": p.N, "tol": p.tol,
+        "config": {"workload": name, "N": p.N, "tol": p.tol, "max_restarts": args.max_restarts,
                    "preconditioner": {binding.MLB_PRECOND_NONE: "none", binding.MLB_PRECOND_JACOBI: "block Jacobi (right)",
                                       binding.MLB_PRECOND_ILU0: "ILU(0) (right)"}[pre]},
         "variants": out,
@@ -504,6 +506,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="number of shadow vectors (0 = the workload's)")
     ap.add_argument("--m", type=int, default=0, help="grid points per dimension (0 = the workload's)")
     ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--max-restarts", type=int, default=0,
+                    help="sequence: restarts from the x reached while the true residual is above tol")
     ap.add_argument("--velocity", default="constant", choices=["constant", "smooth"],
                     help="convdiff3d: one seeded direction (the benchmark's), or a smooth random direction field")
     ap.add_argument("--order", default="fused", choices=["fused", "literal"],

@@ -145,7 +145,22 @@ typedef struct {
   int32_t precond;          /* MLB_PRECOND_NONE, MLB_PRECOND_JACOBI or MLB_PRECOND_ILU0 */
   int32_t transpose_free;   /* 0: Algorithm 7.1 with A^H; 1: without A^H       */
   int32_t order;            /* MLB_ORDER_FUSED (0) or MLB_ORDER_LITERAL (1)    */
+  int32_t max_restarts;     /* fp64: restarts on a residual gap, 0..100 (below) */
 } mlb_options;
+
+/*
+ * max_restarts (an addition of this library; 0 = Algorithm 7.1's own stop):
+ * the fp64 iteration stops when its recursive residual drops below tol
+ * (Algorithm 7.1), and rounding can leave the true residual ||b - A x|| / ||b||
+ * above it.  With max_restarts > 0 the library then starts the iteration
+ * again from the x it reached (a new r_0 = b - A x, the same Q), at most
+ * max_restarts times and within maxit iterations in total, until the true
+ * residual is below tol.  res->iter counts every iteration, res->outer_iters
+ * the restarts; iterates are recorded by the first run only.  Not taken by
+ * the batched one-workgroup solves (mlbicgstab_solve_batch refuses it, the
+ * server runs such requests on the multi-launch iteration) nor by
+ * MLB_PREC_FP32_IR, whose refinement already tests the true residual.
+ */
 
 /*
  * Order of the beta~ and beta recurrences (Algorithm 7.1, the two loops of an
@@ -162,7 +177,7 @@ enum { MLB_ORDER_FUSED = 0, MLB_ORDER_LITERAL = 1 };
 typedef struct {
   int32_t flag;             /* same as the return code when >= -1              */
   int64_t iter;             /* k at exit (fp64), or total inner iterations (IR) */
-  int32_t outer_iters;      /* refinement steps (IR), 0 for fp64               */
+  int32_t outer_iters;      /* refinement steps (IR); fp64: restarts taken     */
   int64_t fp64_iters;       /* iterations run by the fp64 iteration             */
   double err_recursive;     /* recursive ||r_k|| / ||b|| at exit (fp64 iteration) */
   double err_true;          /* ||b - A x|| / ||b|| recomputed in fp64 at exit   */

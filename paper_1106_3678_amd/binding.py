@@ -53,6 +53,7 @@ class mlb_options(ctypes.Structure):
         ("precond", ctypes.c_int32),
         ("transpose_free", ctypes.c_int32),
         ("order", ctypes.c_int32),
+        ("max_restarts", ctypes.c_int32),
     ]
 
 
@@ -386,7 +387,7 @@ class Solver:
     def __init__(self, dmat: DeviceMatrix, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
                  precision: int = MLB_PREC_FP64, inner_tol: float = 0.0, max_outer: int = 0,
                  record_iterates: int = 0, iterates=None, stream=None, precond: int = MLB_PRECOND_NONE,
-                 transpose_free: bool = False, order: int = MLB_ORDER_FUSED):
+                 transpose_free: bool = False, order: int = MLB_ORDER_FUSED, max_restarts: int = 0):
         import torch
 
         self.dmat = dmat
@@ -394,7 +395,7 @@ class Solver:
         self.iterates = iterates
         self.opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, max_outer, record_iterates,
                                iterates.data_ptr() if iterates is not None else None, precond, int(transpose_free),
-                               order)
+                               order, max_restarts)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.h = mlbicgstab_create(dmat.descriptor(), self.opt, self.stream.cuda_stream)
 
@@ -465,12 +466,14 @@ class Sequence:
 
     def __init__(self, dmat: DeviceMatrix, n: int, n_min: int, n_max: int, step: int, tol: float = 1e-10,
                  maxit: int = 1000, kappa: float = 0.0, precision: int = MLB_PREC_FP64, stream=None,
-                 precond: int = MLB_PRECOND_NONE, transpose_free: bool = False, order: int = MLB_ORDER_FUSED):
+                 precond: int = MLB_PRECOND_NONE, transpose_free: bool = False, order: int = MLB_ORDER_FUSED,
+                 max_restarts: int = 0):
         import torch
 
         self.dmat = dmat
         self.n_max = n_max
-        self.opt = mlb_options(n, tol, maxit, kappa, precision, 0.0, 0, 0, None, precond, int(transpose_free), order)
+        self.opt = mlb_options(n, tol, maxit, kappa, precision, 0.0, 0, 0, None, precond, int(transpose_free), order,
+                               max_restarts)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.h = mlb_sequence_create(dmat.descriptor(), self.opt, n_min, n_max, step, self.stream.cuda_stream)
 
@@ -504,11 +507,11 @@ class Server:
 
     def submit(self, dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
                precision: int = MLB_PREC_FP64, inner_tol: float = 0.0, precond: int = MLB_PRECOND_NONE,
-               transpose_free: bool = False, order: int = MLB_ORDER_FUSED) -> int:
+               transpose_free: bool = False, order: int = MLB_ORDER_FUSED, max_restarts: int = 0) -> int:
         N = dmat.nrows
         ldq = q_layout(Q, N, n)
         opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, 0, 0, None, precond, int(transpose_free),
-                          order)
+                          order, max_restarts)
         t = mlb_server_submit(self.h, dmat.descriptor(), opt, b.data_ptr(), x.data_ptr(), Q.data_ptr(), ldq)
         self._keep[t] = (dmat, b, x, Q)
         return t
@@ -516,12 +519,12 @@ class Server:
     def submit_sequence(self, key: int, dmat: DeviceMatrix, b, x, Q, n: int, n_min: int, n_max: int, step: int,
                         tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0, precision: int = MLB_PREC_FP64,
                         inner_tol: float = 0.0, precond: int = MLB_PRECOND_NONE, transpose_free: bool = False,
-                        order: int = MLB_ORDER_FUSED) -> int:
+                        order: int = MLB_ORDER_FUSED, max_restarts: int = 0) -> int:
         """A request of sequence `key` (same A throughout; Q is N x n_max, n is the first request's)."""
         N = dmat.nrows
         ldq = q_layout(Q, N, n_max)
         opt = mlb_options(n, tol, maxit, kappa, precision, inner_tol, 0, 0, None, precond, int(transpose_free),
-                          order)
+                          order, max_restarts)
         t = mlb_server_submit_sequence(self.h, key, dmat.descriptor(), opt, n_min, n_max, step, b.data_ptr(),
                                        x.data_ptr(), Q.data_ptr(), ldq)
         self._keep[t] = (dmat, b, x, Q)

@@ -1147,6 +1147,9 @@ static void check_options(const mlb_options* opt) {
     throw Error{MLB_EINVAL, "order must be MLB_ORDER_FUSED or MLB_ORDER_LITERAL"};
   if (opt->order == MLB_ORDER_LITERAL && opt->transpose_free)
     throw Error{MLB_EUNSUPPORTED, "the literal order is not combined with transpose_free"};
+  if (opt->max_restarts < 0 || opt->max_restarts > 100) throw Error{MLB_EINVAL, "max_restarts must be in [0, 100]"};
+  if (opt->max_restarts > 0 && opt->precision != MLB_PREC_FP64)
+    throw Error{MLB_EUNSUPPORTED, "max_restarts applies to the fp64 iteration"};
   if (opt->record_iterates < 0) throw Error{MLB_EINVAL, "record_iterates must be >= 0"};
   if (opt->record_iterates > 0) {
     if (!opt->iterates) throw Error{MLB_EINVAL, "record_iterates > 0 needs an iterates buffer"};
@@ -1376,6 +1379,22 @@ static int solve_impl(mlb_solver* h, Impl<V64, V32>& im, const V64* b, V64* x, c
     R.fp64_iters = out.iter;
     R.err_recursive = out.err;
     R.setup_ms = out.setup_ms;
+    // restarts from the x reached while a converged run leaves the true residual above tol
+    int restarts = 0;
+    while (flag == 0 && restarts < o.max_restarts && R.iter < o.maxit) {
+      im.e64.resid_sums(im.A0, b, x, im.r64);
+      double rr, bb;
+      im.e64.read_aux(&rr, &bb);
+      const double et = std::sqrt(rr) / (bb > 0 ? std::sqrt(bb) : 1.0);
+      if (!(et >= o.tol)) break;
+      ++restarts;
+      auto more = fp64_iteration(h, im, b, x, Q, ldq, o.maxit - R.iter, (V64*)nullptr, 0);
+      flag = more.flag;
+      R.iter += more.iter;
+      R.fp64_iters += more.iter;
+      R.err_recursive = more.err;
+    }
+    R.outer_iters = restarts;
   } else {
     // fp32 inner iteration inside fp64 iterative refinement (an addition of this library)
     auto& e32 = im.e32;
@@ -1629,6 +1648,7 @@ static void check_batchable(const mlb_solver* h) {
   if (h->opt.precision != MLB_PREC_FP64) throw Error{MLB_EUNSUPPORTED, "batched solves run in fp64"};
   if (h->opt.precond != MLB_PRECOND_NONE) throw Error{MLB_EUNSUPPORTED, "batched solves take no preconditioner"};
   if (h->opt.order != MLB_ORDER_FUSED) throw Error{MLB_EUNSUPPORTED, "batched solves run the fused order"};
+  if (h->opt.max_restarts != 0) throw Error{MLB_EUNSUPPORTED, "batched solves take no restarts"};
   if (h->N > MLB_BATCH_MAX_N) throw Error{MLB_EUNSUPPORTED, "batched solves take at most MLB_BATCH_MAX_N rows"};
 }
 
@@ -2452,7 +2472,8 @@ int mlb_server_submit(mlb_server_handle S, const mlb_matrix* A, const mlb_option
       r->t_submit = now_s();
       S->table[r->ticket] = r;
       r->small = A->format == MLB_CSR && opt->precision == MLB_PREC_FP64 && opt->precond == MLB_PRECOND_NONE &&
-                 opt->record_iterates == 0 && opt->order == MLB_ORDER_FUSED && A->nrows <= S->small_n_max;
+                 opt->record_iterates == 0 && opt->order == MLB_ORDER_FUSED && opt->max_restarts == 0 &&
+                 A->nrows <= S->small_n_max;
       (r->small ? S->small_queue : S->queue).push_back(r);
       *ticket = r->ticket;
     }
@@ -2469,7 +2490,7 @@ static bool same_matrix(const mlb_matrix& a, const mlb_matrix& b) {
 static bool same_options_but_n(const mlb_options& a, const mlb_options& b) {
   return a.tol == b.tol && a.maxit == b.maxit && a.kappa == b.kappa && a.precision == b.precision &&
          a.inner_tol == b.inner_tol && a.max_outer == b.max_outer && a.precond == b.precond &&
-         a.transpose_free == b.transpose_free && a.order == b.order;
+         a.transpose_free == b.transpose_free && a.order == b.order && a.max_restarts == b.max_restarts;
 }
 
 int mlb_server_submit_sequence(mlb_server_handle S, uint64_t key, const mlb_matrix* A, const mlb_options* opt,

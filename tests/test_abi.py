@@ -50,7 +50,7 @@ def _desc(binding, **kw):
 
 def _opt(binding, **kw):
     o = dict(n=4, tol=1e-10, maxit=100, kappa=0.0, precision=0, inner_tol=0.0, max_outer=0, record_iterates=0,
-             iterates=None, precond=0, transpose_free=0, order=0)
+             iterates=None, precond=0, transpose_free=0, order=0, max_restarts=0)
     o.update(kw)
     return binding.mlb_options(**o)
 
@@ -63,6 +63,7 @@ def _opt(binding, **kw):
     dict(o=dict(n=0)), dict(o=dict(tol=0.0)), dict(o=dict(tol=float("nan"))), dict(o=dict(maxit=0)),
     dict(o=dict(kappa=-1.0)), dict(o=dict(precision=5)), dict(o=dict(record_iterates=3)),
     dict(o=dict(precond=7)), dict(o=dict(transpose_free=2)), dict(o=dict(order=5)),
+    dict(o=dict(max_restarts=-1)), dict(o=dict(max_restarts=101)),
 ])
 def test_create_rejects_bad_arguments(binding, bad):
     A = _desc(binding, **bad.get("m", {}))
@@ -77,6 +78,14 @@ def test_create_rejects_bad_arguments(binding, bad):
 def test_literal_order_with_transpose_free_is_unsupported(binding):
     A = _desc(binding)
     o = _opt(binding, order=binding.MLB_ORDER_LITERAL, transpose_free=1)
+    h = binding.mlb_handle()
+    rc = binding.raw_call("mlbicgstab_create", ctypes.byref(A), ctypes.byref(o), None, ctypes.byref(h))
+    assert rc == binding.MLB_EUNSUPPORTED and h.value is None
+
+
+def test_restarts_with_refinement_are_unsupported(binding):
+    A = _desc(binding)
+    o = _opt(binding, precision=binding.MLB_PREC_FP32_IR, max_restarts=1)
     h = binding.mlb_handle()
     rc = binding.raw_call("mlbicgstab_create", ctypes.byref(A), ctypes.byref(o), None, ctypes.byref(h))
     assert rc == binding.MLB_EUNSUPPORTED and h.value is None

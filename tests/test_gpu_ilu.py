@@ -155,6 +155,37 @@ def test_apply_against_oracle(case):
     assert np.array_equal(y, y2), case
 
 
+def test_restart_closes_residual_gap():
+    """The reservoir system with ILU(0), n = 8 and the first right-hand side of the sequence
+    benchmark (seed 1106): the iteration stops on its recursive residual with the true residual
+    above tol.  With max_restarts the library starts again from the x it reached until the true
+    residual is below tol; the first run is the same in both (bitwise), the restarted one adds
+    iterations and reports the restarts."""
+    p = workloads.config3(n=16)
+    b = torch.from_numpy(np.random.default_rng(1106).standard_normal(p.N)).cuda()
+    Q = binding.column_major(p.Q)[:, :8]
+    dA = binding.to_device(p.A)
+    out = {}
+    for mr in (0, 3):
+        x = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+        s = binding.Solver(dA, 8, tol=p.tol, maxit=p.maxit, precond=ILU, max_restarts=mr)
+        try:
+            res = s.solve(b, x, Q)
+            torch.cuda.synchronize()
+        finally:
+            s.close()
+        out[mr] = res
+        print(f"max_restarts={mr}: flag={res.flag} iter={res.iter} restarts={res.outer_iters} "
+              f"err_true={res.err_true:.3e} err_recursive={res.err_recursive:.3e}")
+    r0, r3 = out[0], out[3]
+    assert r0.flag == 0 and r0.outer_iters == 0
+    assert r3.flag == 0 and r3.err_true < p.tol
+    if r0.err_true >= p.tol:
+        assert r3.outer_iters >= 1 and r3.iter > r0.iter
+    else:
+        assert r3.outer_iters == 0 and r3.iter == r0.iter and r3.err_true == r0.err_true
+
+
 def _solver_error(A, opt_precond=ILU, precision=0):
     p = workloads.Problem("e", A, np.ones(A.shape[0]), np.ones((A.shape[0], 1)), np.zeros(A.shape[0]), 1,
                           1e-10, 10)
