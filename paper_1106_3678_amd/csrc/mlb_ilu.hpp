@@ -169,10 +169,11 @@ __device__ inline void ilu_st(unsigned long long* p, unsigned long long v) {
 // One group of (at most) 4 entries of a row: loads the solved values they
 // reference (entries at u >= cnt repeat the last one, unused) and, when none
 // is pending, subtracts a_u x_u from s in entry order.  Returns false, leaving
-// s as it was, while one is pending.
+// s as it was, while one is pending; *waitw then holds the address of a
+// pending word.
 template <class V, int BS>
 __device__ inline bool ilu_group(const V (&a)[4][BS * BS], const int (&c)[4], int cnt, unsigned long long* ow,
-                                 V (&s)[BS]) {
+                                 V (&s)[BS], unsigned long long** waitw) {
   constexpr int W = sizeof(V) / 8;
   using U = unsigned long long;
   U xw[4][BS * W];
@@ -184,7 +185,11 @@ __device__ inline bool ilu_group(const V (&a)[4][BS * BS], const int (&c)[4], in
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int k = 0; k < BS * W; ++k) ready = ready && xw[u][k] != ILU_PENDING;
+    for (int k = 0; k < BS * W; ++k)
+      if (xw[u][k] == ILU_PENDING) {
+        ready = false;
+        *waitw = ow + (size_t)BS * W * c[u] + k;
+      }
   if (!ready) return false;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -268,15 +273,29 @@ __global__ __launch_bounds__(WAVE) void k_ilu_solve_sweep(const int* __restrict_
         for (int e = 0; e < B2; ++e) a0[u][e] = val[(size_t)B2 * q + e];
       }
     }
+    // the diagonal (block) inverse's operand, off the waiting path
+    V dg[UNIT ? 1 : (BS == 1 ? 1 : B2)];
+    if constexpr (!UNIT) {
+      if (pending) {
+        if constexpr (BS == 1) {
+          dg[0] = val[LOWER ? q1 : q0 - 1];
+        } else {
+#pragma unroll
+          for (int e = 0; e < B2; ++e) dg[e] = dinv[(size_t)B2 * i + e];
+        }
+      }
+    }
     const long long t_start = wall_clock64();
     unsigned tries = 0;
+    U* waitw = nullptr;   // a word the last try found pending: polled alone first
     while (__any(pending)) {
       if (pending) {
         V s[BS];
 #pragma unroll
         for (int e = 0; e < BS; ++e) s[e] = s0[e];
-        bool ready = true;
-        if (has0) ready = ilu_group<V, BS>(a0, c0, q1 - q0, ow, s);
+        bool ready = !waitw || ilu_ld(waitw) != ILU_PENDING;
+        if (ready) waitw = nullptr;
+        if (ready && has0) ready = ilu_group<V, BS>(a0, c0, q1 - q0, ow, s, &waitw);
         // further entries in groups of 4, loaded again on every try
         for (int q4 = q0 + 4; q4 < q1 && ready; q4 += 4) {
           int c[4];
@@ -288,7 +307,7 @@ __global__ __launch_bounds__(WAVE) void k_ilu_solve_sweep(const int* __restrict_
 #pragma unroll
             for (int e = 0; e < B2; ++e) a[u][e] = val[(size_t)B2 * q + e];
           }
-          ready = ilu_group<V, BS>(a, c, q1 - q4, ow, s);
+          ready = ilu_group<V, BS>(a, c, q1 - q4, ow, s, &waitw);
         }
         // give up on this row after ILU_WAIT_TICKS, or once another row has (err); both
         // read every 256 tries
@@ -309,14 +328,13 @@ __global__ __launch_bounds__(WAVE) void k_ilu_solve_sweep(const int* __restrict_
 #pragma unroll
               for (int e = 0; e < BS; ++e) o[e] = s[e];
             } else if constexpr (BS == 1) {
-              o[0] = s[0] / val[LOWER ? q1 : q0 - 1];
+              o[0] = s[0] / dg[0];
             } else {
-              const V* di = dinv + (size_t)B2 * i;
 #pragma unroll
               for (int r = 0; r < BS; ++r) {
                 V acc = zero<V>();
 #pragma unroll
-                for (int k = 0; k < BS; ++k) acc = axpy(acc, di[BS * r + k], s[k]);
+                for (int k = 0; k < BS; ++k) acc = axpy(acc, dg[BS * r + k], s[k]);
                 o[r] = acc;
               }
             }
