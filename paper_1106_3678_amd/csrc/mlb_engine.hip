@@ -260,6 +260,7 @@ struct IluFactor {
   V* tmid = nullptr;                  // intermediate vector of the two solves
   unsigned* ctl = nullptr;            // one-launch solves: claim counters [0] and [1], lost-wait flag [2]
   int sweep_grid = 1;                 // their workgroups (persistent: each wave claims until none are left)
+  unsigned max_tries = ~0u;           // tries of a row before it gives up (MLB_ILU_MAX_TRIES, for tests)
 };
 
 // Waves of a one-launch triangular solve, as a multiple of the waves one
@@ -293,7 +294,8 @@ template <class V, int BS, bool LOWER, bool UNIT>
 static void ilu_sweep1(const IluFactor<V>& f, const Mat<V>& M, const V* dinv, const int4* lv, const V* in, V* out,
                        V* next, int which, hipStream_t s, const int* done) {
   k_ilu_solve_sweep<V, BS, LOWER, UNIT><<<f.sweep_grid, WAVE, 0, s>>>(M.ci, M.val, dinv, lv, f.nbrows, in, out,
-                                                                       next, f.ctl + which, f.ctl + 2, done);
+                                                                       next, f.ctl + which, f.ctl + 2, f.max_tries,
+                                                                       done);
 }
 
 // Marks f.tmid pending and resets both claim counters: the start of a pair of one-launch solves.
@@ -384,6 +386,12 @@ static void build_ilu(const Mat<V>& A, IluFactor<V>& f, Allocs& al, hipStream_t 
   f.tmid = al.get<V>((size_t)m * bs);
   f.ctl = al.get<unsigned>(4);
   k_fill<unsigned><<<1, BLOCK, 0, s>>>(f.ctl, 4, 0u);
+  // a test hook: a positive MLB_ILU_MAX_TRIES makes every row that waits that many tries give up
+  // (its solve then fails with MLB_EHIP), so the give-up path can be exercised from the host
+  if (const char* e = std::getenv("MLB_ILU_MAX_TRIES")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v > 0) f.max_tries = (unsigned)std::min<long>(v, 0x7fffffffL);
+  }
   Allocs tmp_own(al.stream, al.ordered);
   int* bad = tmp_own.get<int>(1);
   k_fill<int><<<1, BLOCK, 0, s>>>(bad, 1, 0);

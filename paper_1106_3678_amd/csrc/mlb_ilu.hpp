@@ -227,13 +227,15 @@ __global__ void k_ilu_pending(unsigned long long* __restrict__ w, long long nw, 
 // must hold the pending mark (k_ilu_pending) and may not overlap in.  next: the
 // output of the solve that follows, or null: row i of it is marked pending
 // once in_i is read (so next may be in).  tick: this solve's claim counter, 0
-// at launch; err: set to 1 when a wait ran past its bound.  done: the solve's
-// done flag (the launch returns at once when it is set), or null.
+// at launch; err: set to 1 when a wait ran past its bound; max_tries: tries of
+// one row before it gives up regardless of time (~0u: no such limit; a small
+// value forces the give-up path in tests).  done: the solve's done flag (the
+// launch returns at once when it is set), or null.
 template <class V, int BS, bool LOWER, bool UNIT>
 __global__ __launch_bounds__(WAVE) void k_ilu_solve_sweep(const int* __restrict__ ci, const V* __restrict__ val,
                                                           const V* __restrict__ dinv, const int4* __restrict__ lv,
                                                           int m, const V* in, V* out, V* next, unsigned* tick,
-                                                          unsigned* err, const int* done) {
+                                                          unsigned* err, unsigned max_tries, const int* done) {
   constexpr int B2 = BS * BS;
   constexpr int W = sizeof(V) / 8;   // 64-bit words per value (1 real, 2 complex)
   using U = unsigned long long;
@@ -309,12 +311,14 @@ __global__ __launch_bounds__(WAVE) void k_ilu_solve_sweep(const int* __restrict_
           }
           ready = ilu_group<V, BS>(a, c, q1 - q4, ow, s, &waitw);
         }
-        // give up on this row after ILU_WAIT_TICKS, or once another row has (err); both
-        // read every 256 tries
+        // give up on this row after ILU_WAIT_TICKS, or once another row has (err), both
+        // read every 256 tries, or after max_tries tries
         bool lost = false;
-        if (!ready && (++tries & 255u) == 0) {
-          lost = wall_clock64() - t_start > ILU_WAIT_TICKS ||
-                 __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        if (!ready) {
+          ++tries;
+          lost = tries >= max_tries ||
+                 ((tries & 255u) == 0 && (wall_clock64() - t_start > ILU_WAIT_TICKS ||
+                                          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0));
           if (lost) atomicOr(err, 1u);
         }
         if (ready || lost) {

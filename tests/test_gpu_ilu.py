@@ -186,6 +186,22 @@ def test_restart_closes_residual_gap():
         assert r3.outer_iters == 0 and r3.iter == r0.iter and r3.err_true == r0.err_true
 
 
+def test_wait_give_up_reports_error(monkeypatch):
+    """The bounded wait of the one-launch triangular solves, forced from the host: with
+    MLB_ILU_MAX_TRIES=1 a row not ready at its first try gives up (stored as a quiet NaN, every
+    launch still ends) and the solve returns MLB_EHIP.  On the 32 x 32 grid one wave claims the
+    first 64 rows, which span several levels, so some row always waits.  A solver built without
+    the limit then solves the same system normally."""
+    p = workloads.config1(n=4)
+    monkeypatch.setenv("MLB_ILU_MAX_TRIES", "1")
+    with pytest.raises(binding.MlbError) as e:
+        run_gpu(p, precond=ILU)
+    assert e.value.code == binding.MLB_EHIP and "gave up" in str(e.value)
+    monkeypatch.delenv("MLB_ILU_MAX_TRIES")
+    res, x, _ = run_gpu(p, precond=ILU)
+    assert res.flag == 0 and res.err_true < p.tol
+
+
 def _solver_error(A, opt_precond=ILU, precision=0):
     p = workloads.Problem("e", A, np.ones(A.shape[0]), np.ones((A.shape[0], 1)), np.zeros(A.shape[0]), 1,
                           1e-10, 10)
