@@ -156,10 +156,12 @@ typedef struct {
  * again from the x it reached (a new r_0 = b - A x, the same Q), at most
  * max_restarts times and within maxit iterations in total, until the true
  * residual is below tol.  res->iter counts every iteration, res->outer_iters
- * the restarts; iterates are recorded by the first run only.  Not taken by
- * the batched one-workgroup solves (mlbicgstab_solve_batch refuses it, the
- * server runs such requests on the multi-launch iteration) nor by
- * MLB_PREC_FP32_IR, whose refinement already tests the true residual.
+ * the restarts; iterates are recorded by the first run only.
+ * mlbicgstab_solve_batch refuses it; the server runs a small request on its
+ * batched one-workgroup solve first and, if that leaves the true residual
+ * not below tol, restarts it from its x on the multi-launch iteration.  Not
+ * taken by MLB_PREC_FP32_IR, whose refinement already tests the true
+ * residual.
  */
 
 /*

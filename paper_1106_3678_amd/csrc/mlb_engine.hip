@@ -2332,7 +2332,9 @@ static void batcher_main(Server* S) {
       for (size_t k = 0; k < batch.size(); ++k) {
         Request& r = *batch[k];
         try {
-          hs[k] = create_solver(&r.A, &r.opt, st, true, flags + 2 * k);
+          mlb_options ob = r.opt;   // the batched run itself takes no restarts (see below)
+          ob.max_restarts = 0;
+          hs[k] = create_solver(&r.A, &ob, st, true, flags + 2 * k);
           run.push_back(hs[k].get());
           bs.push_back(r.b);
           xs.push_back(r.x);
@@ -2385,6 +2387,37 @@ static void batcher_main(Server* S) {
       }
       for (auto& h : hs) h.reset();
       (void)hipStreamSynchronize(st);
+      // a request with restarts whose batched run converged with its true residual not below
+      // tol goes on from its x on the multi-launch iteration, within its admitted footprint
+      for (size_t k = 0; k < batch.size(); ++k) {
+        Request& r = *batch[k];
+        if (r.rc != 0 || r.opt.max_restarts <= 0 || !(r.res.err_true >= r.opt.tol) || r.res.iter >= r.opt.maxit)
+          continue;
+        try {
+          mlb_options o2 = r.opt;
+          o2.max_restarts = r.opt.max_restarts - 1;
+          o2.maxit = r.opt.maxit - r.res.iter;
+          auto h2 = create_solver(&r.A, &o2, st, true, flags + 2 * k);
+          mlb_result r2{};
+          const int rc2 = solve_solver(h2.get(), r.b, r.x, r.Q, r.ldq, &r2);
+          h2.reset();
+          (void)hipStreamSynchronize(st);
+          r.res.iter += r2.iter;
+          r.res.fp64_iters += r2.fp64_iters;
+          r.res.outer_iters = 1 + r2.outer_iters;
+          r.res.err_true = r2.err_true;
+          r.res.err_recursive = r2.err_recursive;
+          r.res.solve_ms += r2.solve_ms;
+          r.res.flag = rc2;
+          r.rc = rc2;
+        } catch (const Error& e) {
+          r.rc = e.code;
+          r.err = e.msg;
+        } catch (const std::exception& e) {
+          r.rc = MLB_EHIP;
+          r.err = e.what();
+        }
+      }
     }
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -2480,8 +2513,7 @@ int mlb_server_submit(mlb_server_handle S, const mlb_matrix* A, const mlb_option
       r->t_submit = now_s();
       S->table[r->ticket] = r;
       r->small = A->format == MLB_CSR && opt->precision == MLB_PREC_FP64 && opt->precond == MLB_PRECOND_NONE &&
-                 opt->record_iterates == 0 && opt->order == MLB_ORDER_FUSED && opt->max_restarts == 0 &&
-                 A->nrows <= S->small_n_max;
+                 opt->record_iterates == 0 && opt->order == MLB_ORDER_FUSED && A->nrows <= S->small_n_max;
       (r->small ? S->small_queue : S->queue).push_back(r);
       *ticket = r->ticket;
     }

@@ -260,6 +260,53 @@ def test_sequence_in_server_follows_the_rule_and_matches_fresh_solves():
         assert torch.equal(xf, x)
 
 
+def _batched(p, tol):
+    dA, b, x, Q = upload(p)
+    s = binding.Solver(dA, p.n, tol=tol, maxit=p.maxit)
+    try:
+        return binding.solve_batch([s], [b], [x], [Q])[0]
+    finally:
+        s.close()
+
+
+def _served(p, tol, max_restarts):
+    dA, b, x, Q = upload(p)
+    torch.cuda.synchronize()
+    server = binding.Server(budget_bytes=8 << 30, max_inflight=1)
+    try:
+        res, _ = server.wait(server.submit(dA, b, x, Q, p.n, tol=tol, maxit=p.maxit, max_restarts=max_restarts))
+    finally:
+        server.close()
+    r = b.cpu().numpy() - p.A @ x.cpu().numpy()
+    return res, np.linalg.norm(r) / np.linalg.norm(p.b)
+
+
+def test_batched_request_restarts_on_residual_gap():
+    """A small request on the batched solve that stops on its recursive residual with the true residual
+    not below tol.  Such a case is made by setting tol between the two residuals of a run at 1e-10:
+    the run then stops at the same iteration (the one before it was still above).  Served with
+    max_restarts = 0 the request comes back with the gap.  With max_restarts = 2 the server restarts
+    it from its x on the multi-launch iteration.  The result then reports the restart and the added
+    iterations, and its true residual (also recomputed here on the CPU) is below tol."""
+    checked = 0
+    for m, n in ((32, 2), (48, 8), (64, 2), (64, 4)):
+        p = workloads.config1(n=n, m=m)
+        ref = _batched(p, 1e-10)
+        if not ref.err_true > ref.err_recursive:
+            continue
+        tol = float(np.sqrt(ref.err_true * ref.err_recursive))
+        r0, e0 = _served(p, tol, 0)
+        if not (r0.flag == 0 and r0.err_true >= tol):
+            continue
+        r2, e2 = _served(p, tol, 2)
+        print(f"m={m} n={n} tol={tol:.4e}: without restarts iter={r0.iter} err_true={r0.err_true:.4e}; "
+              f"with: iter={r2.iter} restarts={r2.outer_iters} err_true={r2.err_true:.4e} (CPU {e2:.4e})")
+        assert r2.flag == 0 and r2.outer_iters >= 1 and r2.iter > r0.iter
+        assert r2.err_true < tol and e2 < 1.01 * tol
+        checked += 1
+    assert checked >= 1, "no candidate system showed a residual gap"
+
+
 def test_sequence_argument_errors():
     p = workloads.config1(n=4)
     dA, b, x, Q = upload(p)
