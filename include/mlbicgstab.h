@@ -116,8 +116,12 @@ typedef struct {
  * level of the row dependencies; the level sets come from a host pass over a
  * copy of A's index arrays) and fails with MLB_EINVAL for a (block) row without
  * a stored diagonal, a column stored twice in a row, or a zero / singular
- * pivot.  The triangular solves take one launch per level: 3m - 2 levels each
- * on an m^3 7-point grid.  fp64 only (MLB_EUNSUPPORTED with MLB_PREC_FP32_IR).
+ * pivot.  Each triangular solve is one launch that takes the rows in level
+ * order (3m - 2 levels on an m^3 7-point grid), every row waiting for the
+ * solved values it reads; a wait is bounded (2 s), and a solve in which one
+ * ran out returns MLB_EHIP (the environment variable MLB_ILU_MAX_TRIES, read
+ * by create(), bounds the tries of a row instead: a test hook for that path).
+ * fp64 only (MLB_EUNSUPPORTED with MLB_PREC_FP32_IR).
  *
  * transpose_free = 1 runs the iteration without A^H (an addition of this
  * library; Section 4 names A^H-free algorithms but prints only their costs).
