@@ -234,8 +234,7 @@ static void level_sets(const std::vector<int>& rp, const std::vector<int>& ci, b
   for (int i = 0; i < m; ++i) order[fill[lev[i]]++] = i;
 }
 
-// The ILU(0) factor of A, its conjugate transpose and the level sets of the
-// four triangular solves (L, U of the factor; U^H, L^H of its transpose).
+// Compute units of the current device (256 if the query fails).
 static int device_cus() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
@@ -246,6 +245,9 @@ static int device_cus() {
   return cus;
 }
 
+// The ILU(0) factor of A, its conjugate transpose and the rows of the four
+// triangular solves in level order (L, U of the factor; U^H, L^H of its
+// transpose).
 template <class V>
 struct IluFactor {
   int bs = 1, nbrows = 0;
@@ -1325,7 +1327,7 @@ static bool debug_enabled() {
 }
 
 // Throws when a one-launch triangular solve gave up a wait since the last check
-// (the flag is cleared first, so the factor stays usable).
+// (the flag is cleared before the error is raised, so the factor stays usable).
 template <class V>
 static void ilu_check(const IluFactor<V>& f, hipStream_t s) {
   unsigned e = 0;
