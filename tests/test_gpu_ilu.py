@@ -132,12 +132,46 @@ def _apply_both(p, seed=5):
     return y.cpu().numpy(), yh.cpu().numpy(), y2.cpu().numpy(), apply(v), apply_h(v)
 
 
-@pytest.mark.parametrize("case", ["2d", "2d_ragged", "3d", "complex", "bsr3", "bsr3_larger", "full_128"])
+def _random_rows(N, per_row, seed, cplx=False, block=False):
+    """A diagonally dominant matrix with about per_row random entries (3x3 blocks when block) a row:
+    rows with more than 4 entries on each side of the diagonal, unlike the stencil matrices."""
+    g = np.random.default_rng(seed)
+    nb = N // 3 if block else N
+    rows = np.repeat(np.arange(nb), per_row)
+    P = sp.csr_matrix((np.ones(nb * per_row), (rows, g.integers(0, nb, nb * per_row))), shape=(nb, nb))
+    P = (P + sp.identity(nb, format="csr")).tocsr()
+    P.sum_duplicates()
+    P.sort_indices()
+    bs = 3 if block else 1
+    data = g.standard_normal((P.nnz, bs, bs))
+    if cplx:
+        data = data + 1j * g.standard_normal((P.nnz, bs, bs))
+    rowsum = np.zeros(nb)
+    np.add.at(rowsum, np.repeat(np.arange(nb), np.diff(P.indptr)), np.abs(data).sum(axis=(1, 2)))
+    for i in range(nb):   # diagonal (blocks) dominant
+        for q in range(P.indptr[i], P.indptr[i + 1]):
+            if P.indices[q] == i:
+                data[q] += (rowsum[i] + 1.0) * np.eye(bs)
+    if block:
+        A = sp.bsr_matrix((data, P.indices, P.indptr), shape=(3 * nb, 3 * nb))
+    else:
+        A = sp.csr_matrix((data[:, 0, 0], P.indices, P.indptr), shape=(nb, nb))
+    N = A.shape[0]
+    dt = np.complex128 if cplx else np.float64
+    return workloads.Problem("random_rows", A, np.ones(N, dtype=dt), np.ones((N, 1), dtype=dt), np.zeros(N, dtype=dt),
+                             1, 1e-10, 100)
+
+
+@pytest.mark.parametrize("case", ["2d", "2d_ragged", "3d", "complex", "bsr3", "bsr3_larger", "full_128", "csr_long_rows",
+                                  "csr_long_rows_complex", "bsr3_long_rows_complex"])
 def test_apply_against_oracle(case):
     """One application of M^{-1} and of M^{-H} element by element against the oracle's factor and
     triangular solves.  Both sides form the same factor (the same products in the same order, up to
-    the fma contraction) and substitute in row order, so they differ by rounding only (6.4e-16 of the
-    largest entry at most in these cases); the bar is 1e-12 of it (the achieved value is printed).  A second application of the
+    the fma contraction) and substitute in row order, so they differ by rounding only (9.3e-16 of the
+    largest entry at most in these cases); the bar is 1e-12 of it (the achieved value is printed).
+    The random-pattern cases have rows with up to 14 entries on a side (the stencils at most 3), so
+    the entries past a row's first four, loaded again on every try, are covered too, and complex
+    3x3 blocks.  A second application of the
     same v is bitwise the first: each row's sum runs in entry order, whichever wave solves it and
     whenever the values it reads arrive."""
     p = {"2d": lambda: workloads.config1(n=4),
@@ -146,7 +180,10 @@ def test_apply_against_oracle(case):
          "complex": lambda: workloads.config5(n=4, m=12),
          "bsr3": lambda: workloads.config3(n=4, grid=(8, 10, 6)),
          "bsr3_larger": lambda: workloads.config3(n=4, grid=(20, 60, 30)),
-         "full_128": lambda: workloads.config2(n=4, m=128)}[case]()
+         "full_128": lambda: workloads.config2(n=4, m=128),
+         "csr_long_rows": lambda: _random_rows(3000, 14, 1),
+         "csr_long_rows_complex": lambda: _random_rows(2000, 14, 2, cplx=True),
+         "bsr3_long_rows_complex": lambda: _random_rows(1200, 12, 3, cplx=True, block=True)}[case]()
     y, yh, y2, yo, yho = _apply_both(p)
     for name, a, ref in (("M^-1", y, yo), ("M^-H", yh, yho)):
         err = np.max(np.abs(a - ref)) / np.max(np.abs(ref))
