@@ -10,8 +10,9 @@ fp64-refinement mode (--precision ir) use the same step definition.
 
 The default line also carries, under "secondary", one record per other
 configuration (the reservoir system in fp64 and fp32-IR, the complex system
-with n = 16, and the 2000-request serving trace in fp32-IR beside the same
-requests solved one after another in fp64); --no-extras leaves them out.
+with n = 16, the 128^3 system with ILU(0) at n = 1 and n = 4, and the
+2000-request serving trace in fp64 and fp32-IR beside the same requests
+solved one after another in fp64); --no-extras leaves them out.
 Prints one JSON line.  Progress goes to stderr.
 """
 import argparse
@@ -524,7 +525,7 @@ def main():
                     help="cap on the oracle sample (iterations); 0: about 15 s of CPU time")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the secondary workloads (reservoir fp64 / fp32-IR, complex n = 16, serving)")
+                    help="skip the secondary workloads (reservoir fp64 / fp32-IR, complex n = 16, ILU(0), serving)")
     ap.add_argument("--extra-steps", type=int, default=2, help="timed solves per secondary workload")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--calib-copy", type=float, default=0.0,
@@ -733,7 +734,8 @@ def timed_solves(torch, binding, p, dev, precision, precond, transpose_free, ord
 def secondary_workloads(args, torch, workloads, binding, dev):
     """The other configurations of the benchmark, one line each, so that every headline claim has a
     measured record: the reservoir system in fp64 and in fp32-IR, the complex Helmholtz system with
-    n = 16, and the serving trace in fp32-IR beside the same requests as sequential fp64 solves."""
+    n = 16, the 128^3 system with ILU(0) (the paper's preconditioner) for BiCGStab (n = 1) and ML(4),
+    and the serving trace in fp64 and fp32-IR beside the same requests as sequential fp64 solves."""
     out = {}
     for name, wl, precs in (("reservoir_n8", "reservoir", ("fp64", "ir")), ("helmholtz_m96_n16", "helmholtz", ("fp64",))):
         t = time.perf_counter()
@@ -760,6 +762,18 @@ def secondary_workloads(args, torch, workloads, binding, dev):
         if "ir" in rec:
             rec["ir_vs_fp64_time"] = rec["ir"]["ms_per_solve"] / rec["fp64"]["ms_per_solve"]
         out[name] = rec
+    # ILU(0): BiCGStab (n = 1) against ML(4) on the 128^3 system, the setting of Section 5.2
+    rec = {"preconditioner": "ILU(0) (right)", "steps": args.extra_steps, "warmup": 1}
+    for n in (1, 4):
+        p, _, _, _ = make_problem("convdiff3d", workloads, n=n)
+        r = timed_solves(torch, binding, p, dev, "fp64", binding.MLB_PRECOND_ILU0, False, "fused", args.extra_steps, 1)
+        last = r["last"]
+        rec[f"n{n}"] = {"ms_per_solve": r["ms"], "iterations": int(last.iter), "flag": int(last.flag),
+                        "err_true": last.err_true, "create_ms": r["create_ms"]}
+        dA_keep.clear()
+        torch.cuda.empty_cache()
+    rec["reduction_n4_vs_bicgstab"] = 1.0 - rec["n4"]["ms_per_solve"] / rec["n1"]["ms_per_solve"]
+    out["convdiff3d_m128_ilu0"] = rec
     sargs = argparse.Namespace(**vars(args))
     sargs.transpose_free = False
     generated = serving_items(sargs, torch, workloads, binding)
