@@ -434,7 +434,7 @@ class Solver:
 
 def solve_noalloc(dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit: int = 1000, kappa: float = 0.0,
                   record_iterates: int = 0, iterates=None, stream=None, transpose_free: bool = False,
-                  order: int = MLB_ORDER_FUSED) -> mlb_result:
+                  order: int = MLB_ORDER_FUSED, max_restarts: int = 0) -> mlb_result:
     """mlbicgstab_solve_noalloc: one fp64 solve with every library buffer in the static device scratch."""
     import torch
 
@@ -444,7 +444,7 @@ def solve_noalloc(dmat: DeviceMatrix, b, x, Q, n: int, tol: float = 1e-10, maxit
         raise ValueError("b and x must be contiguous vectors of length N")
     opt = mlb_options(n, tol, maxit, kappa, MLB_PREC_FP64, 0.0, 0, record_iterates,
                       iterates.data_ptr() if iterates is not None else None, MLB_PRECOND_NONE, int(transpose_free),
-                      order)
+                      order, max_restarts)
     st = stream if stream is not None else torch.cuda.current_stream()
     return mlbicgstab_solve_noalloc(dmat.descriptor(), opt, st.cuda_stream, b.data_ptr(), x.data_ptr(),
                                     Q.data_ptr(), ldq)

@@ -93,3 +93,46 @@ def test_noalloc_largest_fitting_system_and_rejection():
     # the same system fits without A^H
     r = _same(big, transpose_free=True)
     assert r.flag == 0
+
+
+def test_noalloc_restarts_match_create_solve():
+    """max_restarts through the allocation-free entry point.  A converged run whose true residual is
+    not below tol is made by setting tol between the two residuals of a reference run at 1e-10 (the
+    run then stops at the same iteration).  With max_restarts = 2 the solve restarts from its x, with
+    every buffer in the static scratch, and the result is bitwise that of create + solve + destroy with
+    the same options."""
+
+    def create_solve(p, tol, mr):
+        dA, b, Q, tdt = _upload(p)
+        x = torch.zeros(p.N, dtype=tdt, device="cuda")
+        s = binding.Solver(dA, p.n, tol=tol, maxit=p.maxit, max_restarts=mr)
+        try:
+            res = s.solve(b, x, Q)
+            torch.cuda.synchronize()
+        finally:
+            s.close()
+        return res, x.cpu().numpy()
+
+    checked = 0
+    for m, n in ((32, 2), (48, 8), (64, 2), (64, 4)):
+        p = workloads.config1(n=n, m=m)
+        ref, _ = create_solve(p, 1e-10, 0)
+        if not ref.err_true > ref.err_recursive:
+            continue
+        tol = float(np.sqrt(ref.err_true * ref.err_recursive))
+        r0, _ = create_solve(p, tol, 0)
+        if not (r0.flag == 0 and r0.err_true >= tol):
+            continue
+        r2, x2 = create_solve(p, tol, 2)
+        dA, b, Q, tdt = _upload(p)
+        x = torch.zeros(p.N, dtype=tdt, device="cuda")
+        print(f"[noalloc] restarts m={m} n={n} tol={tol:.4e}", flush=True)
+        rn = binding.solve_noalloc(dA, b, x, Q, p.n, tol=tol, maxit=p.maxit, max_restarts=2)
+        torch.cuda.synchronize()
+        print(f"  create/solve: iter={r2.iter} restarts={r2.outer_iters} err_true={r2.err_true:.4e}; "
+              f"noalloc: iter={rn.iter} restarts={rn.outer_iters} err_true={rn.err_true:.4e}")
+        assert r2.flag == 0 and r2.outer_iters >= 1 and r2.err_true < tol
+        assert (rn.flag, rn.iter, rn.outer_iters) == (r2.flag, r2.iter, r2.outer_iters)
+        assert np.array_equal(x.cpu().numpy(), x2) and rn.err_true == r2.err_true
+        checked += 1
+    assert checked >= 1, "no candidate system showed a residual gap"
