@@ -163,7 +163,8 @@ def _random_rows(N, per_row, seed, cplx=False, block=False):
 
 
 @pytest.mark.parametrize("case", ["2d", "2d_ragged", "3d", "complex", "bsr3", "bsr3_larger", "full_128", "csr_long_rows",
-                                  "csr_long_rows_complex", "bsr3_long_rows_complex"])
+                                  "csr_long_rows_complex", "bsr3_long_rows_complex", "tiny_1", "tiny_7",
+                                  "tiny_bsr3_2", "tiny_63"])
 def test_apply_against_oracle(case):
     """One application of M^{-1} and of M^{-H} element by element against the oracle's factor and
     triangular solves.  Both sides form the same factor (the same products in the same order, up to
@@ -183,7 +184,12 @@ def test_apply_against_oracle(case):
          "full_128": lambda: workloads.config2(n=4, m=128),
          "csr_long_rows": lambda: _random_rows(3000, 14, 1),
          "csr_long_rows_complex": lambda: _random_rows(2000, 14, 2, cplx=True),
-         "bsr3_long_rows_complex": lambda: _random_rows(1200, 12, 3, cplx=True, block=True)}[case]()
+         "bsr3_long_rows_complex": lambda: _random_rows(1200, 12, 3, cplx=True, block=True),
+         # every level inside the first 64 positions: one wave, rows waiting on rows of the same wave
+         "tiny_1": lambda: _random_rows(1, 1, 5),
+         "tiny_7": lambda: _random_rows(7, 4, 6),
+         "tiny_bsr3_2": lambda: _random_rows(6, 2, 7, cplx=True, block=True),
+         "tiny_63": lambda: _random_rows(63, 5, 8)}[case]()
     y, yh, y2, yo, yho = _apply_both(p)
     for name, a, ref in (("M^-1", y, yo), ("M^-H", yh, yho)):
         err = np.max(np.abs(a - ref)) / np.max(np.abs(ref))
