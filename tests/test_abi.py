@@ -191,3 +191,45 @@ def test_sequence_create_rejects_bad_bounds(binding):
     assert binding.raw_call("mlb_sequence_solve", None, None, None, None, ctypes.c_int64(1), ctypes.byref(res),
                             None) == binding.MLB_EINVAL
     assert binding.raw_call("mlb_sequence_destroy", None) == 0
+
+
+STRUCTS = ("mlb_matrix", "mlb_options", "mlb_result", "mlb_server_options", "mlb_request_timing",
+           "mlb_server_stats_t")
+
+
+def test_binding_structs_and_constants_match_the_header(binding, tmp_path):
+    """The ctypes structs have the header's sizes and field offsets, and every enum constant of the
+    header has the binding's value: a C program compiled with gcc against include/mlbicgstab.h
+    prints sizeof and offsetof of each binding field (a field the header lacks fails to compile)."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "%s"' % HEADER, "int main(void) {"]
+    for sname in STRUCTS:
+        st = getattr(binding, sname)
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (sname, sname))
+        for fname, _ in st._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (sname, fname, sname, fname))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c11", "-o", str(exe), str(src)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                  text=True).stdout.splitlines())
+    for sname in STRUCTS:
+        st = getattr(binding, sname)
+        assert int(out[sname]) == ctypes.sizeof(st), sname
+        for fname, _ in st._fields_:
+            assert int(out[f"{sname}.{fname}"]) == getattr(st, fname).offset, (sname, fname)
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    consts = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", text, flags=re.S):
+        for name, val in re.findall(r"(MLB_\w+)\s*=\s*(-?\d+)", body):
+            consts[name] = int(val)
+    assert len(consts) >= 20
+    for name, val in consts.items():
+        assert getattr(binding, name) == val, name
